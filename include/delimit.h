@@ -1,0 +1,195 @@
+/*
+ * delimit.h -- C ABI of libdelimit.so, an MI355X (gfx950) implementation of
+ * the DELIMIT diffusion-imaging layers (Koppers & Merhof, arXiv:1808.01517):
+ * Signal2SH and SH2Signal (Sec. 2.2) and the local spherical convolution
+ * with cyclic kernels, single- and multi-shell (Sec. 2.3 and 2.3.1).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Plain C: no C++ or torch types.  Voxel counts are int64_t.  A stream
+ *   is a hipStream_t passed as void* (NULL = the default stream).
+ * - Pointers documented "device" must point to device memory of the current
+ *   HIP device; "host" pointers are ordinary CPU memory.  All device data at
+ *   the ABI is row-major float32; the caller owns every activation,
+ *   gradient, weight and workspace buffer.  Plans own their device tables.
+ * - Compute calls are asynchronous on the given stream and never allocate;
+ *   they validate every argument on the host before any launch and return a
+ *   dlm_status.  No C++ exception crosses the ABI.  On error nothing has been
+ *   launched and dlm_last_error() describes the problem (thread-local).
+ * - Results are deterministic: no floating-point atomics; reductions run in
+ *   a fixed order for a given (V, workspace size).
+ * - Real even-order SH of order L (even, 0..16) have K = (L+1)(L+2)/2
+ *   coefficients, index j = l(l+1)/2 + m; m<0 uses sqrt2 N P_l^|m| cos(|m|phi),
+ *   m=0 N P_l, m>0 sqrt2 N P_l^m sin(m phi), Condon-Shortley phase included.
+ */
+#ifndef DELIMIT_H
+#define DELIMIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DLM_OK = 0,
+  DLM_EINVAL = 1,      /* invalid argument: NULL pointer, size, order, NaN   */
+  DLM_ESINGULAR = 2,   /* a fit's normal matrix is not positive definite     */
+  DLM_ENOMEM = 3,      /* allocation failed (plan creation only)             */
+  DLM_EDEVICE = 4,     /* HIP runtime error (no device, launch, copy)        */
+  DLM_EWORKSPACE = 5   /* workspace smaller than the minimum                 */
+} dlm_status;
+
+/* Arithmetic form.  DLM_FP32: float32 inputs and products, float32
+ * accumulation.  DLM_BF16: matrix-core inputs rounded to bfloat16 (round to
+ * nearest even) with float32 accumulation; tables are formed in float64 and
+ * rounded once.  Storage at the ABI is float32 in both forms. */
+typedef enum { DLM_FP32 = 0, DLM_BF16 = 1 } dlm_precision;
+
+const char *dlm_status_str(dlm_status s);
+/* Last error message of the calling thread ("" if none). */
+const char *dlm_last_error(void);
+/* Library ABI version, currently 1. */
+int dlm_version(void);
+
+/* ------------------------------------------------------------------------
+ * Host-only float64 tables (no device needed; for inspection and tests).
+ * ------------------------------------------------------------------------ */
+
+/* SH basis B[i][j] = Y_j(dir_i), dirs host [n][3] (normalised internally),
+ * B host [n][K].  Sec. 2.2 (the layers' spherical-harmonic representation). */
+dlm_status dlm_sh_basis(int sh_order, const double *dirs, int64_t n, double *B);
+
+/* Regularised least-squares fit P = (B^T B + lambda L)^{-1} B^T with
+ * L = diag(l^2 (l+1)^2) (Laplace-Beltrami penalty, Signal2SH's lb_lambda,
+ * Sec. 2.2).  dirs host [n][3]; P host [K][n].  DLM_ESINGULAR when the
+ * normal matrix is not positive definite (e.g. lambda = 0 with n < K). */
+dlm_status dlm_sh_fit_matrix(int sh_order, const double *dirs, int64_t n, double lb_lambda, double *P);
+
+/* Cyclic-kernel points (Sec. 2.3, Fig. 3): for every direction g_i the
+ * centre g_i followed by ring r = 1..R of kernel_sizes[r-1] points at
+ * angular distance r * angular_distance / R (radians), azimuth 2 pi b / n_r
+ * measured from e_theta toward e_phi.  g host [m][3]; points host [m][T][3],
+ * T = 1 + sum(kernel_sizes). */
+dlm_status dlm_lsc_kernel_points(const double *g, int64_t m, const int *kernel_sizes, int n_rings,
+                                 double angular_distance, double *points);
+
+/* ------------------------------------------------------------------------
+ * SH plan: one gradient table (Signal2SH / SH2Signal parameters, Sec. 2.2)
+ * ------------------------------------------------------------------------ */
+typedef struct dlm_sh_plan dlm_sh_plan;
+
+/* Build the per-shell basis B_s [N_s][K] and fit P_s [K][N_s] in float64 on
+ * the host and upload float32 and bfloat16 copies to the current device.
+ * bvecs host [n][3], bvals host [n].  Volumes with b < b0_max are b=0
+ * volumes and are dropped (the layers take b0-normalised signal); the rest
+ * are grouped into shells (b within shell_rel_tol of a shell's mean b),
+ * ordered by increasing b, volumes within a shell in table order.
+ * Signal arrays at the ABI are shell-major: [V][N_dw] = shell 0's N_0
+ * values, then shell 1's ...  *out receives the plan (free with
+ * dlm_sh_plan_destroy). */
+dlm_status dlm_sh_plan_create(const double *bvecs, const double *bvals, int64_t n, int sh_order,
+                              double lb_lambda, double b0_max, double shell_rel_tol, dlm_sh_plan **out);
+/* n_shells, K and total diffusion-weighted count N_dw (any may be NULL). */
+dlm_status dlm_sh_plan_info(const dlm_sh_plan *plan, int *n_shells, int *K, int64_t *n_dw);
+/* Shell s: direction count, mean b, and (if volume_index != NULL) the
+ * index into the creation table of each of its n_dirs volumes. */
+dlm_status dlm_sh_plan_shell(const dlm_sh_plan *plan, int shell, int64_t *n_dirs, double *b,
+                             int64_t *volume_index);
+/* Host float64 copies of B_s [N_s][K] and P_s [K][N_s] (either may be NULL). */
+dlm_status dlm_sh_plan_matrices(const dlm_sh_plan *plan, int shell, double *B, double *P);
+/* Replace the directions (same n and b-values as at creation, e.g. a fresh
+ * per-scan distortion) and rebuild every table in float64; the upload is
+ * ordered on `stream`, so calls already queued on it use the old tables. */
+dlm_status dlm_sh_plan_update_gradients(dlm_sh_plan *plan, const double *bvecs, void *stream);
+void dlm_sh_plan_destroy(dlm_sh_plan *plan);
+
+/* Signal2SH (Sec. 2.2): c[v][s][:] = P_s x[v][s-block].
+ * x device [V][N_dw] (b0-normalised), c device [V][S][K]. */
+dlm_status dlm_signal2sh_fwd(const dlm_sh_plan *plan, const float *x, float *c, int64_t V,
+                             dlm_precision prec, void *stream);
+/* Adjoint of Signal2SH: dx[v][s-block] = P_s^T dc[v][s][:]. */
+dlm_status dlm_signal2sh_bwd(const dlm_sh_plan *plan, const float *dc, float *dx, int64_t V,
+                             dlm_precision prec, void *stream);
+/* SH2Signal (Sec. 2.2): x[v][s-block] = B_s c[v][s][:].
+ * c device [V][S][K], x device [V][N_dw]. */
+dlm_status dlm_sh2signal_fwd(const dlm_sh_plan *plan, const float *c, float *x, int64_t V,
+                             dlm_precision prec, void *stream);
+/* Adjoint of SH2Signal: dc[v][s][:] = B_s^T dx[v][s-block]. */
+dlm_status dlm_sh2signal_bwd(const dlm_sh_plan *plan, const float *dx, float *dc, int64_t V,
+                             dlm_precision prec, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Local spherical convolution (Sec. 2.3, multi-b-value form Sec. 2.3.1)
+ * ------------------------------------------------------------------------ */
+typedef struct dlm_lsc_plan dlm_lsc_plan;
+
+/* Geometry of one LSC layer: m sampled directions (sampled_gradients host
+ * [m][3]), input order sh_order_in, output order sh_order_out, cyclic
+ * kernel rings kernel_sizes[n_rings] (points per ring), outer-ring angular
+ * distance (radians), refit penalty lb_lambda.  Builds in float64 and
+ * uploads: the resampling basis B_nb [m*T][K_in] (SH interpolation at every
+ * kernel point) and the refit P_m [K_out][m]. */
+dlm_status dlm_lsc_plan_create(const double *sampled_gradients, int64_t m, int sh_order_in,
+                               int sh_order_out, const int *kernel_sizes, int n_rings,
+                               double angular_distance, double lb_lambda, dlm_lsc_plan **out);
+/* T = kernel taps, K_in, K_out, m (any may be NULL). */
+dlm_status dlm_lsc_plan_info(const dlm_lsc_plan *plan, int *T, int *K_in, int *K_out, int64_t *m);
+/* Host float64 tables: points [m][T][3], B_nb [m*T][K_in], P_m [K_out][m]
+ * (any may be NULL). */
+dlm_status dlm_lsc_plan_tables(const dlm_lsc_plan *plan, double *points, double *B_nb, double *P_m);
+void dlm_lsc_plan_destroy(dlm_lsc_plan *plan);
+
+/* Workspace bytes that dlm_lsc_fwd / dlm_lsc_bwd need to process `V_chunk`
+ * voxels per pass for C input and O output channels.  A call given fewer
+ * bytes than needed for its V processes the voxels in several passes; the
+ * minimum is the size for one 64-voxel pass (less -> DLM_EWORKSPACE). */
+dlm_status dlm_lsc_workspace_bytes(const dlm_lsc_plan *plan, int C, int O, int64_t V_chunk,
+                                   dlm_precision prec, size_t *bytes);
+
+/* LSC forward in the paper's order (Sec. 2.3, Fig. 4):
+ *   X[v][c][i*T+t] = sum_j B_nb[i*T+t][j] a_in[v][c][j]   (neighbourhood resampling)
+ *   y[v][o][i]     = bias[o] + sum_c sum_t W[o][c][t] X[v][c][i*T+t]
+ *                    (kernel row dot, a cross-correlation; channels = b-values)
+ *   a_out[v][o][:] = P_m y[v][o][:]                        (refit)
+ *   optional ReLU: a_out = max(a_out, 0) when fuse_relu != 0.
+ * a_in device [V][C][K_in]; W device [O][C][T]; bias device [O] or NULL;
+ * a_out device [V][O][K_out]; ws device workspace of ws_bytes. */
+dlm_status dlm_lsc_fwd(const dlm_lsc_plan *plan, const float *a_in, int C, const float *W,
+                       const float *bias, int O, float *a_out, int64_t V, int fuse_relu, void *ws,
+                       size_t ws_bytes, dlm_precision prec, void *stream);
+
+/* Adjoint of dlm_lsc_fwd.  da_out device [V][O][K_out] is the gradient of the
+ * layer output; if fused_relu != 0 it is masked by a_out > 0 (a_out device
+ * [V][O][K_out], the forward's output).  Outputs (each may be NULL to skip):
+ *   da_in device [V][C][K_in]   = B_nb^T (sum_o W dy),  dy = P_m^T da
+ *   dW    device [O][C][T]      = sum_{v,i} dy[v][o][i] X[v][c][i*T+t] (overwritten)
+ *   dbias device [O]            = sum_{v,i} dy[v][o][i]                (overwritten)
+ * The neighbourhood matrices X are recomputed from a_in, not stored. */
+dlm_status dlm_lsc_bwd(const dlm_lsc_plan *plan, const float *a_in, int C, const float *W, int O,
+                       const float *a_out, const float *da_out, float *da_in, float *dW, float *dbias,
+                       int64_t V, int fused_relu, void *ws, size_t ws_bytes, dlm_precision prec,
+                       void *stream);
+
+/* ------------------------------------------------------------------------
+ * Training helpers (q-space loss, Sec. 1; optimiser)
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of workspace dlm_mse_fwd_bwd needs for n elements. */
+size_t dlm_mse_workspace_bytes(int64_t n);
+/* loss (device scalar) = mean((pred - target)^2) over n elements;
+ * dpred device [n] = 2 (pred - target) / n (NULL to skip). */
+dlm_status dlm_mse_fwd_bwd(const float *pred, const float *target, int64_t n, float *loss, float *dpred,
+                           void *ws, size_t ws_bytes, void *stream);
+
+/* One Adam step on n parameters (device w, g, m, v), bias-corrected with the
+ * 1-based step count. */
+dlm_status dlm_adam_step(float *w, const float *g, float *m, float *v, int64_t n, float lr, float beta1,
+                         float beta2, float eps, int64_t step, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DELIMIT_H */

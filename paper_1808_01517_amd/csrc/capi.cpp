@@ -1,0 +1,726 @@
+// C ABI of libdelimit: plan creation (float64 tables built on the host and
+// uploaded once), argument validation before any launch, workspace
+// chunking, and the launch sequence of each layer call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace dlm {
+int lsc_weight_splits(int64_t V, int m, int target);
+}
+
+using namespace dlm;
+
+namespace {
+
+thread_local std::string g_err;
+
+dlm_status fail(dlm_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+dlm_status ok() {
+  g_err.clear();
+  return DLM_OK;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+bool have_device() {
+  int n = 0;
+  return hipGetDeviceCount(&n) == hipSuccess && n > 0;
+}
+
+bool upload(DevMat &d, const std::vector<double> &h, int rows, int cols, hipStream_t st, std::vector<float> &sf,
+            std::vector<uint16_t> &sh) {
+  const size_t n = size_t(rows) * cols;
+  d.rows = rows;
+  d.cols = cols;
+  if (!d.f32 && hipMalloc(&d.f32, std::max<size_t>(n, 1) * sizeof(float)) != hipSuccess) return false;
+  if (!d.bf16 && hipMalloc(&d.bf16, std::max<size_t>(n, 1) * sizeof(uint16_t)) != hipSuccess) return false;
+  sf.resize(n);
+  sh.resize(n);
+  for (size_t i = 0; i < n; ++i) {
+    sf[i] = float(h[i]);
+    sh[i] = f64_to_bf16_rne(h[i]);
+  }
+  if (hipMemcpyAsync(d.f32, sf.data(), n * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess) return false;
+  if (hipMemcpyAsync(d.bf16, sh.data(), n * sizeof(uint16_t), hipMemcpyHostToDevice, st) != hipSuccess) return false;
+  return true;
+}
+
+void release(DevMat &d) {
+  if (d.f32) (void)hipFree(d.f32);
+  if (d.bf16) (void)hipFree(d.bf16);
+  d.f32 = nullptr;
+  d.bf16 = nullptr;
+}
+
+std::vector<double> transpose(const std::vector<double> &a, int rows, int cols) {
+  std::vector<double> t(size_t(rows) * cols);
+  for (int r = 0; r < rows; ++r)
+    for (int c = 0; c < cols; ++c) t[size_t(c) * rows + r] = a[size_t(r) * cols + c];
+  return t;
+}
+
+bool finite_all(const double *p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- plans
+struct dlm_sh_plan {
+  int L = 0, K = 0, S = 0;
+  double lambda = 0, b0_max = 0, rel_tol = 0;
+  int64_t n_total = 0, n_dw = 0;
+  std::vector<std::vector<int64_t>> members;
+  std::vector<double> shell_b;
+  std::vector<int64_t> dirs, offs;
+  std::vector<std::vector<double>> B, P;  // host float64, B_s [N_s][K], P_s [K][N_s]
+  bool uniform = true;
+  // device, all shells back to back: P [S][K][N], Pt [S][N][K], B [S][N][K], Bt [S][K][N]
+  DevMat dP, dPt, dB, dBt;
+  std::vector<float> stage_f;
+  std::vector<uint16_t> stage_h;
+  hipEvent_t staged = nullptr;
+};
+
+struct dlm_lsc_plan {
+  int64_t m = 0;
+  int T = 0, L_in = 0, L_out = 0, K_in = 0, K_out = 0;
+  std::vector<int> ks;
+  double alpha = 0, lambda = 0;
+  std::vector<double> g, points, Bnb, Pm;
+  DevMat dBnb, dBnbT, dPm, dPmT;
+};
+
+namespace {
+
+dlm_status sh_build_tables(dlm_sh_plan *p, const double *bvecs) {
+  p->B.assign(p->S, {});
+  p->P.assign(p->S, {});
+  for (int s = 0; s < p->S; ++s) {
+    const int64_t n = p->dirs[s];
+    std::vector<double> u(size_t(n) * 3);
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t src = p->members[s][i];
+      if (!unit_dir(bvecs + 3 * src, u.data() + 3 * i))
+        return fail(DLM_EINVAL, "gradient %lld (b=%g) is zero or not finite", (long long)src, p->shell_b[s]);
+    }
+    p->B[s].resize(size_t(n) * p->K);
+    p->P[s].resize(size_t(n) * p->K);
+    sh_basis_unit(p->L, u.data(), n, p->B[s].data());
+    if (!fit_from_basis(p->L, p->B[s].data(), n, p->lambda, p->P[s].data()))
+      return fail(DLM_ESINGULAR, "shell %d (b=%g): normal matrix of %lld directions at order %d is singular", s,
+                  p->shell_b[s], (long long)n, p->L);
+  }
+  return DLM_OK;
+}
+
+dlm_status sh_upload(dlm_sh_plan *p, hipStream_t st) {
+  if (p->staged) (void)hipEventSynchronize(p->staged);  // staging buffers free again
+  std::vector<double> P, Pt, B, Bt;
+  for (int s = 0; s < p->S; ++s) {
+    const int n = int(p->dirs[s]);
+    P.insert(P.end(), p->P[s].begin(), p->P[s].end());
+    auto pt = transpose(p->P[s], p->K, n);
+    Pt.insert(Pt.end(), pt.begin(), pt.end());
+    B.insert(B.end(), p->B[s].begin(), p->B[s].end());
+    auto bt = transpose(p->B[s], n, p->K);
+    Bt.insert(Bt.end(), bt.begin(), bt.end());
+  }
+  const int total = int(p->n_dw);
+  // Each table goes through its own staging slice so earlier async copies
+  // never see a buffer overwritten by a later one.
+  DevMat *dst[4] = {&p->dP, &p->dPt, &p->dB, &p->dBt};
+  const std::vector<double> *src[4] = {&P, &Pt, &B, &Bt};
+  const size_t n = size_t(total) * p->K;
+  p->stage_f.resize(4 * n);
+  p->stage_h.resize(4 * n);
+  for (int t = 0; t < 4; ++t) {
+    DevMat &d = *dst[t];
+    if (!d.f32 && hipMalloc(&d.f32, n * sizeof(float)) != hipSuccess) return fail(DLM_ENOMEM, "hipMalloc failed");
+    if (!d.bf16 && hipMalloc(&d.bf16, n * sizeof(uint16_t)) != hipSuccess) return fail(DLM_ENOMEM, "hipMalloc failed");
+    float *f = p->stage_f.data() + t * n;
+    uint16_t *h = p->stage_h.data() + t * n;
+    for (size_t i = 0; i < n; ++i) {
+      f[i] = float((*src[t])[i]);
+      h[i] = f64_to_bf16_rne((*src[t])[i]);
+    }
+    if (hipMemcpyAsync(d.f32, f, n * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(d.bf16, h, n * sizeof(uint16_t), hipMemcpyHostToDevice, st) != hipSuccess)
+      return fail(DLM_EDEVICE, "table upload failed: %s", hipGetErrorString(hipGetLastError()));
+  }
+  if (!p->staged && hipEventCreateWithFlags(&p->staged, hipEventDisableTiming) != hipSuccess)
+    return fail(DLM_EDEVICE, "hipEventCreate failed");
+  if (hipEventRecord(p->staged, st) != hipSuccess) return fail(DLM_EDEVICE, "hipEventRecord failed");
+  return DLM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dlm_status_str(dlm_status s) {
+  switch (s) {
+    case DLM_OK: return "ok";
+    case DLM_EINVAL: return "invalid argument";
+    case DLM_ESINGULAR: return "singular fit";
+    case DLM_ENOMEM: return "out of memory";
+    case DLM_EDEVICE: return "device error";
+    case DLM_EWORKSPACE: return "workspace too small";
+  }
+  return "unknown status";
+}
+
+const char *dlm_last_error(void) { return g_err.c_str(); }
+
+int dlm_version(void) { return 1; }
+
+dlm_status dlm_sh_basis(int sh_order, const double *dirs, int64_t n, double *B) {
+  if (!sh_order_ok(sh_order)) return fail(DLM_EINVAL, "sh_order %d must be even and in [0, %d]", sh_order, kMaxShOrder);
+  if (n < 0 || (n > 0 && (!dirs || !B))) return fail(DLM_EINVAL, "null pointer or negative n");
+  const int K = sh_num_coeffs(sh_order);
+  for (int64_t i = 0; i < n; ++i) {
+    double u[3];
+    if (!unit_dir(dirs + 3 * i, u)) return fail(DLM_EINVAL, "direction %lld is zero or not finite", (long long)i);
+    sh_row(sh_order, u, B + i * K);
+  }
+  return ok();
+}
+
+dlm_status dlm_sh_fit_matrix(int sh_order, const double *dirs, int64_t n, double lb_lambda, double *P) {
+  if (!sh_order_ok(sh_order)) return fail(DLM_EINVAL, "sh_order %d must be even and in [0, %d]", sh_order, kMaxShOrder);
+  if (n <= 0 || !dirs || !P) return fail(DLM_EINVAL, "null pointer or n <= 0");
+  if (!(lb_lambda >= 0.0) || !std::isfinite(lb_lambda)) return fail(DLM_EINVAL, "lb_lambda must be finite and >= 0");
+  const int K = sh_num_coeffs(sh_order);
+  std::vector<double> B(size_t(n) * K);
+  dlm_status s = dlm_sh_basis(sh_order, dirs, n, B.data());
+  if (s != DLM_OK) return s;
+  if (!fit_from_basis(sh_order, B.data(), n, lb_lambda, P))
+    return fail(DLM_ESINGULAR, "normal matrix of %lld directions at order %d is singular", (long long)n, sh_order);
+  return ok();
+}
+
+dlm_status dlm_lsc_kernel_points(const double *g, int64_t m, const int *kernel_sizes, int n_rings,
+                                 double angular_distance, double *points) {
+  if (m <= 0 || !g || !points || !kernel_sizes) return fail(DLM_EINVAL, "null pointer or m <= 0");
+  if (n_rings < 1) return fail(DLM_EINVAL, "need at least one ring");
+  int T = 1;
+  for (int r = 0; r < n_rings; ++r) {
+    if (kernel_sizes[r] < 1) return fail(DLM_EINVAL, "ring %d has %d points", r, kernel_sizes[r]);
+    T += kernel_sizes[r];
+  }
+  if (T > kMaxTaps) return fail(DLM_EINVAL, "kernel has %d taps (max %d)", T, kMaxTaps);
+  if (!(angular_distance > 0.0) || !(angular_distance < 3.14159265358979323846))
+    return fail(DLM_EINVAL, "angular_distance must be in (0, pi) radians");
+  std::vector<double> u(size_t(m) * 3);
+  for (int64_t i = 0; i < m; ++i)
+    if (!unit_dir(g + 3 * i, u.data() + 3 * i)) return fail(DLM_EINVAL, "direction %lld is zero or not finite", (long long)i);
+  kernel_points_unit(u.data(), m, kernel_sizes, n_rings, angular_distance, points);
+  return ok();
+}
+
+// ----------------------------------------------------------------- SH plan
+dlm_status dlm_sh_plan_create(const double *bvecs, const double *bvals, int64_t n, int sh_order, double lb_lambda,
+                              double b0_max, double shell_rel_tol, dlm_sh_plan **out) {
+  if (!out) return fail(DLM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!bvecs || !bvals || n <= 0) return fail(DLM_EINVAL, "null table or n <= 0");
+  if (!sh_order_ok(sh_order)) return fail(DLM_EINVAL, "sh_order %d must be even and in [0, %d]", sh_order, kMaxShOrder);
+  if (!(lb_lambda >= 0.0) || !std::isfinite(lb_lambda)) return fail(DLM_EINVAL, "lb_lambda must be finite and >= 0");
+  if (!std::isfinite(b0_max) || !(shell_rel_tol >= 0.0) || !(shell_rel_tol < 1.0))
+    return fail(DLM_EINVAL, "b0_max must be finite and shell_rel_tol in [0, 1)");
+  if (!finite_all(bvals, n)) return fail(DLM_EINVAL, "b-values must be finite");
+  if (!have_device()) return fail(DLM_EDEVICE, "no HIP device is available");
+  dlm_sh_plan *p = new (std::nothrow) dlm_sh_plan();
+  if (!p) return fail(DLM_ENOMEM, "host allocation failed");
+  p->L = sh_order;
+  p->K = sh_num_coeffs(sh_order);
+  p->lambda = lb_lambda;
+  p->b0_max = b0_max;
+  p->rel_tol = shell_rel_tol;
+  p->n_total = n;
+  group_shells(bvals, n, b0_max, shell_rel_tol, p->members, p->shell_b);
+  p->S = int(p->members.size());
+  if (p->S == 0) {
+    delete p;
+    return fail(DLM_EINVAL, "no diffusion-weighted volumes (all b < %g)", b0_max);
+  }
+  int64_t off = 0;
+  for (int s = 0; s < p->S; ++s) {
+    p->dirs.push_back(int64_t(p->members[s].size()));
+    p->offs.push_back(off);
+    off += p->dirs.back();
+    if (p->dirs[s] != p->dirs[0]) p->uniform = false;
+  }
+  p->n_dw = off;
+  dlm_status s = sh_build_tables(p, bvecs);
+  if (s == DLM_OK) s = sh_upload(p, nullptr);
+  if (s == DLM_OK && hipStreamSynchronize(nullptr) != hipSuccess) s = fail(DLM_EDEVICE, "upload failed");
+  if (s != DLM_OK) {
+    dlm_sh_plan_destroy(p);
+    return s;
+  }
+  *out = p;
+  return ok();
+}
+
+dlm_status dlm_sh_plan_info(const dlm_sh_plan *p, int *n_shells, int *K, int64_t *n_dw) {
+  if (!p) return fail(DLM_EINVAL, "plan is NULL");
+  if (n_shells) *n_shells = p->S;
+  if (K) *K = p->K;
+  if (n_dw) *n_dw = p->n_dw;
+  return ok();
+}
+
+dlm_status dlm_sh_plan_shell(const dlm_sh_plan *p, int shell, int64_t *n_dirs, double *b, int64_t *volume_index) {
+  if (!p) return fail(DLM_EINVAL, "plan is NULL");
+  if (shell < 0 || shell >= p->S) return fail(DLM_EINVAL, "shell %d out of range [0, %d)", shell, p->S);
+  if (n_dirs) *n_dirs = p->dirs[shell];
+  if (b) *b = p->shell_b[shell];
+  if (volume_index) std::copy(p->members[shell].begin(), p->members[shell].end(), volume_index);
+  return ok();
+}
+
+dlm_status dlm_sh_plan_matrices(const dlm_sh_plan *p, int shell, double *B, double *P) {
+  if (!p) return fail(DLM_EINVAL, "plan is NULL");
+  if (shell < 0 || shell >= p->S) return fail(DLM_EINVAL, "shell %d out of range [0, %d)", shell, p->S);
+  if (B) std::copy(p->B[shell].begin(), p->B[shell].end(), B);
+  if (P) std::copy(p->P[shell].begin(), p->P[shell].end(), P);
+  return ok();
+}
+
+dlm_status dlm_sh_plan_update_gradients(dlm_sh_plan *p, const double *bvecs, void *stream) {
+  if (!p || !bvecs) return fail(DLM_EINVAL, "plan or bvecs is NULL");
+  auto saved_B = p->B;
+  auto saved_P = p->P;
+  dlm_status s = sh_build_tables(p, bvecs);
+  if (s != DLM_OK) {
+    p->B = saved_B;
+    p->P = saved_P;
+    return s;
+  }
+  s = sh_upload(p, (hipStream_t)stream);
+  return s == DLM_OK ? ok() : s;
+}
+
+void dlm_sh_plan_destroy(dlm_sh_plan *p) {
+  if (!p) return;
+  if (p->staged) {
+    (void)hipEventSynchronize(p->staged);
+    (void)hipEventDestroy(p->staged);
+  }
+  release(p->dP);
+  release(p->dPt);
+  release(p->dB);
+  release(p->dBt);
+  delete p;
+}
+
+namespace {
+
+enum class ShOp { S2shFwd, S2shBwd, Sh2sFwd, Sh2sBwd };
+
+dlm_status sh_apply(const dlm_sh_plan *p, const float *in, float *out, int64_t V, dlm_precision prec, void *stream,
+                    ShOp op) {
+  if (!p) return fail(DLM_EINVAL, "plan is NULL");
+  if (V < 0) return fail(DLM_EINVAL, "V must be >= 0");
+  if (prec != DLM_FP32 && prec != DLM_BF16) return fail(DLM_EINVAL, "unknown precision %d", int(prec));
+  if (V == 0) return ok();
+  if (!in || !out) return fail(DLM_EINVAL, "null device pointer");
+  const int K = p->K, S = p->S;
+  const int64_t ndw = p->n_dw;
+  // signal side: [V][ndw], coefficient side: [V][S][K]
+  const bool to_coef = (op == ShOp::S2shFwd || op == ShOp::Sh2sBwd);
+  const DevMat &tab = op == ShOp::S2shFwd ? p->dP : op == ShOp::S2shBwd ? p->dPt : op == ShOp::Sh2sFwd ? p->dB : p->dBt;
+  const int shells = p->uniform ? 1 : S;
+  for (int s0 = 0; s0 < shells; ++s0) {
+    const int64_t N = p->dirs[s0];
+    TableGemm t;
+    t.M = V;
+    t.groups = p->uniform ? S : 1;
+    const int64_t sig_off = p->uniform ? 0 : p->offs[s0];
+    const int64_t coef_off = p->uniform ? 0 : int64_t(s0) * K;
+    const int64_t tab_off = sig_off * K;  // tables are back to back: offs[s] * K
+    if (to_coef) {
+      t.A = in + sig_off;
+      t.lda = ndw;
+      t.a_gs = N;
+      t.C = out + coef_off;
+      t.ldc = int64_t(S) * K;
+      t.c_gs = K;
+      t.N = K;
+      t.K = int(N);
+    } else {
+      t.A = in + coef_off;
+      t.lda = int64_t(S) * K;
+      t.a_gs = K;
+      t.C = out + sig_off;
+      t.ldc = ndw;
+      t.c_gs = N;
+      t.N = int(N);
+      t.K = K;
+    }
+    t.Bf = tab.f32 + tab_off;
+    t.Bh = tab.bf16 + tab_off;
+    t.b_gs = N * K;
+    if (launch_table_gemm(t, prec, stream) != 0)
+      return fail(DLM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
+  }
+  return ok();
+}
+
+}  // namespace
+
+dlm_status dlm_signal2sh_fwd(const dlm_sh_plan *p, const float *x, float *c, int64_t V, dlm_precision prec, void *st) {
+  return sh_apply(p, x, c, V, prec, st, ShOp::S2shFwd);
+}
+dlm_status dlm_signal2sh_bwd(const dlm_sh_plan *p, const float *dc, float *dx, int64_t V, dlm_precision prec, void *st) {
+  return sh_apply(p, dc, dx, V, prec, st, ShOp::S2shBwd);
+}
+dlm_status dlm_sh2signal_fwd(const dlm_sh_plan *p, const float *c, float *x, int64_t V, dlm_precision prec, void *st) {
+  return sh_apply(p, c, x, V, prec, st, ShOp::Sh2sFwd);
+}
+dlm_status dlm_sh2signal_bwd(const dlm_sh_plan *p, const float *dx, float *dc, int64_t V, dlm_precision prec, void *st) {
+  return sh_apply(p, dx, dc, V, prec, st, ShOp::Sh2sBwd);
+}
+
+// ----------------------------------------------------------------- LSC plan
+dlm_status dlm_lsc_plan_create(const double *sampled_gradients, int64_t m, int sh_order_in, int sh_order_out,
+                               const int *kernel_sizes, int n_rings, double angular_distance, double lb_lambda,
+                               dlm_lsc_plan **out) {
+  if (!out) return fail(DLM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!sh_order_ok(sh_order_in) || !sh_order_ok(sh_order_out))
+    return fail(DLM_EINVAL, "sh orders (%d, %d) must be even and in [0, %d]", sh_order_in, sh_order_out, kMaxShOrder);
+  if (!(lb_lambda >= 0.0) || !std::isfinite(lb_lambda)) return fail(DLM_EINVAL, "lb_lambda must be finite and >= 0");
+  if (m > (int64_t(1) << 20)) return fail(DLM_EINVAL, "m = %lld sampled directions is too many", (long long)m);
+  if (!have_device()) return fail(DLM_EDEVICE, "no HIP device is available");
+  dlm_lsc_plan *p = new (std::nothrow) dlm_lsc_plan();
+  if (!p) return fail(DLM_ENOMEM, "host allocation failed");
+  p->m = m;
+  p->L_in = sh_order_in;
+  p->L_out = sh_order_out;
+  p->K_in = sh_num_coeffs(sh_order_in);
+  p->K_out = sh_num_coeffs(sh_order_out);
+  p->alpha = angular_distance;
+  p->lambda = lb_lambda;
+  if (n_rings >= 1 && kernel_sizes) p->ks.assign(kernel_sizes, kernel_sizes + n_rings);
+  p->T = 1;
+  for (int k : p->ks) p->T += k;
+  p->points.resize(size_t(std::max<int64_t>(m, 0)) * p->T * 3);
+  dlm_status s = dlm_lsc_kernel_points(sampled_gradients, m, kernel_sizes, n_rings, angular_distance, p->points.data());
+  if (s != DLM_OK) {
+    delete p;
+    return s;
+  }
+  p->g.resize(size_t(m) * 3);
+  for (int64_t i = 0; i < m; ++i) unit_dir(sampled_gradients + 3 * i, p->g.data() + 3 * i);
+  const int64_t P = m * p->T;
+  p->Bnb.resize(size_t(P) * p->K_in);
+  sh_basis_unit(p->L_in, p->points.data(), P, p->Bnb.data());
+  std::vector<double> Bm(size_t(m) * p->K_out);
+  sh_basis_unit(p->L_out, p->g.data(), m, Bm.data());
+  p->Pm.resize(size_t(m) * p->K_out);
+  if (!fit_from_basis(p->L_out, Bm.data(), m, lb_lambda, p->Pm.data())) {
+    delete p;
+    return fail(DLM_ESINGULAR, "refit: normal matrix of %lld directions at order %d is singular", (long long)m,
+                sh_order_out);
+  }
+  std::vector<float> sf;
+  std::vector<uint16_t> shh;
+  bool good = upload(p->dBnb, p->Bnb, int(P), p->K_in, nullptr, sf, shh) && hipStreamSynchronize(nullptr) == hipSuccess;
+  good = good && upload(p->dBnbT, transpose(p->Bnb, int(P), p->K_in), p->K_in, int(P), nullptr, sf, shh) &&
+         hipStreamSynchronize(nullptr) == hipSuccess;
+  good = good && upload(p->dPm, p->Pm, p->K_out, int(m), nullptr, sf, shh) && hipStreamSynchronize(nullptr) == hipSuccess;
+  good = good && upload(p->dPmT, transpose(p->Pm, p->K_out, int(m)), int(m), p->K_out, nullptr, sf, shh) &&
+         hipStreamSynchronize(nullptr) == hipSuccess;
+  if (!good) {
+    dlm_lsc_plan_destroy(p);
+    return fail(DLM_EDEVICE, "table upload failed: %s", hipGetErrorString(hipGetLastError()));
+  }
+  *out = p;
+  return ok();
+}
+
+dlm_status dlm_lsc_plan_info(const dlm_lsc_plan *p, int *T, int *K_in, int *K_out, int64_t *m) {
+  if (!p) return fail(DLM_EINVAL, "plan is NULL");
+  if (T) *T = p->T;
+  if (K_in) *K_in = p->K_in;
+  if (K_out) *K_out = p->K_out;
+  if (m) *m = p->m;
+  return ok();
+}
+
+dlm_status dlm_lsc_plan_tables(const dlm_lsc_plan *p, double *points, double *B_nb, double *P_m) {
+  if (!p) return fail(DLM_EINVAL, "plan is NULL");
+  if (points) std::copy(p->points.begin(), p->points.end(), points);
+  if (B_nb) std::copy(p->Bnb.begin(), p->Bnb.end(), B_nb);
+  if (P_m) std::copy(p->Pm.begin(), p->Pm.end(), P_m);
+  return ok();
+}
+
+void dlm_lsc_plan_destroy(dlm_lsc_plan *p) {
+  if (!p) return;
+  release(p->dBnb);
+  release(p->dBnbT);
+  release(p->dPm);
+  release(p->dPmT);
+  delete p;
+}
+
+namespace {
+
+constexpr int kWeightSplitTarget = 256;
+constexpr int64_t kMinChunk = 64;
+
+struct LscWs {
+  float *Wt = nullptr;
+  uint16_t *Wh = nullptr, *Wth = nullptr;
+  float *X = nullptr, *y = nullptr, *part = nullptr;
+};
+
+size_t lsc_ws_need(const dlm_lsc_plan *p, int C, int O, int64_t Vc) {
+  const size_t CTO = size_t(C) * p->T * O;
+  const size_t P = size_t(p->m) * p->T;
+  size_t b = align256(CTO * 4) + 2 * align256(CTO * 2);
+  b += align256(size_t(Vc) * C * P * 4);
+  b += align256(size_t(Vc) * O * p->m * 4);
+  b += align256(size_t(kWeightSplitTarget) * (size_t(C) * p->T + 1) * O * 4);
+  return b;
+}
+
+LscWs lsc_ws_carve(const dlm_lsc_plan *p, int C, int O, int64_t Vc, void *ws) {
+  LscWs w;
+  char *b = static_cast<char *>(ws);
+  const size_t CTO = size_t(C) * p->T * O;
+  const size_t P = size_t(p->m) * p->T;
+  w.Wt = reinterpret_cast<float *>(b);
+  b += align256(CTO * 4);
+  w.Wh = reinterpret_cast<uint16_t *>(b);
+  b += align256(CTO * 2);
+  w.Wth = reinterpret_cast<uint16_t *>(b);
+  b += align256(CTO * 2);
+  w.X = reinterpret_cast<float *>(b);
+  b += align256(size_t(Vc) * C * P * 4);
+  w.y = reinterpret_cast<float *>(b);
+  b += align256(size_t(Vc) * O * p->m * 4);
+  w.part = reinterpret_cast<float *>(b);
+  return w;
+}
+
+// Largest chunk (multiple of kMinChunk unless V is smaller) whose workspace fits.
+int64_t lsc_chunk(const dlm_lsc_plan *p, int C, int O, int64_t V, size_t ws_bytes) {
+  int64_t hi = std::max<int64_t>(V, 1);
+  // keep (chunk * m) within int range for the reduction index
+  hi = std::min<int64_t>(hi, (int64_t(1) << 30) / std::max<int64_t>(p->m, 1));
+  if (lsc_ws_need(p, C, O, hi) <= ws_bytes) return hi;
+  int64_t lo = std::min<int64_t>(V, kMinChunk);
+  if (lsc_ws_need(p, C, O, lo) > ws_bytes) return 0;
+  // binary search on multiples of kMinChunk
+  int64_t a = 1, b = hi / kMinChunk;
+  if (b < 1) return lo;
+  while (a < b) {
+    const int64_t mid = (a + b + 1) / 2;
+    if (lsc_ws_need(p, C, O, mid * kMinChunk) <= ws_bytes) a = mid;
+    else b = mid - 1;
+  }
+  return a * kMinChunk;
+}
+
+dlm_status lsc_check(const dlm_lsc_plan *p, int C, int O, int64_t V, dlm_precision prec) {
+  if (!p) return fail(DLM_EINVAL, "plan is NULL");
+  if (C < 1 || C > kMaxChannels || O < 1 || O > kMaxChannels)
+    return fail(DLM_EINVAL, "channels C=%d O=%d must be in [1, %d]", C, O, kMaxChannels);
+  if (V < 0) return fail(DLM_EINVAL, "V must be >= 0");
+  if (prec != DLM_FP32 && prec != DLM_BF16) return fail(DLM_EINVAL, "unknown precision %d", int(prec));
+  return DLM_OK;
+}
+
+dlm_status launched(int rc) {
+  if (rc == 0) return DLM_OK;
+  return fail(DLM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
+}
+
+}  // namespace
+
+dlm_status dlm_lsc_workspace_bytes(const dlm_lsc_plan *p, int C, int O, int64_t V_chunk, dlm_precision prec,
+                                   size_t *bytes) {
+  dlm_status s = lsc_check(p, C, O, V_chunk, prec);
+  if (s != DLM_OK) return s;
+  if (!bytes) return fail(DLM_EINVAL, "bytes is NULL");
+  *bytes = lsc_ws_need(p, C, O, std::max<int64_t>(V_chunk, 1));
+  return ok();
+}
+
+dlm_status dlm_lsc_fwd(const dlm_lsc_plan *p, const float *a_in, int C, const float *W, const float *bias, int O,
+                       float *a_out, int64_t V, int fuse_relu, void *ws, size_t ws_bytes, dlm_precision prec,
+                       void *stream) {
+  dlm_status s = lsc_check(p, C, O, V, prec);
+  if (s != DLM_OK) return s;
+  if (V == 0) return ok();
+  if (!a_in || !W || !a_out || !ws) return fail(DLM_EINVAL, "null device pointer");
+  const int64_t Vc = lsc_chunk(p, C, O, V, ws_bytes);
+  if (Vc == 0)
+    return fail(DLM_EWORKSPACE, "workspace of %zu bytes is below the %zu-byte minimum", ws_bytes,
+                lsc_ws_need(p, C, O, std::min<int64_t>(V, kMinChunk)));
+  LscWs w = lsc_ws_carve(p, C, O, Vc, ws);
+  const int T = p->T, m = int(p->m);
+  const int64_t P = p->m * T;
+  if ((s = launched(launch_prepare_weights(W, w.Wt, w.Wh, w.Wth, C, O, T, stream))) != DLM_OK) return s;
+  for (int64_t v0 = 0; v0 < V; v0 += Vc) {
+    const int64_t nv = std::min(Vc, V - v0);
+    TableGemm rs;  // resampling: X[(v,c)][p] = sum_j B_nb[p][j] a[(v,c)][j]
+    rs.A = a_in + v0 * C * p->K_in;
+    rs.lda = p->K_in;
+    rs.Bf = p->dBnb.f32;
+    rs.Bh = p->dBnb.bf16;
+    rs.C = w.X;
+    rs.ldc = P;
+    rs.M = nv * C;
+    rs.N = int(P);
+    rs.K = p->K_in;
+    if ((s = launched(launch_table_gemm(rs, prec, stream))) != DLM_OK) return s;
+    if ((s = launched(launch_lsc_contract_fwd(w.X, W, w.Wh, bias, w.y, nv, C, O, m, T, prec, stream))) != DLM_OK)
+      return s;
+    TableGemm rf;  // refit: a_out[(v,o)][k] = sum_i P_m[k][i] y[(v,o)][i]
+    rf.A = w.y;
+    rf.lda = m;
+    rf.Bf = p->dPm.f32;
+    rf.Bh = p->dPm.bf16;
+    rf.C = a_out + v0 * O * p->K_out;
+    rf.ldc = p->K_out;
+    rf.M = nv * O;
+    rf.N = p->K_out;
+    rf.K = m;
+    rf.relu = fuse_relu ? 1 : 0;
+    if ((s = launched(launch_table_gemm(rf, prec, stream))) != DLM_OK) return s;
+  }
+  return ok();
+}
+
+dlm_status dlm_lsc_bwd(const dlm_lsc_plan *p, const float *a_in, int C, const float *W, int O, const float *a_out,
+                       const float *da_out, float *da_in, float *dW, float *dbias, int64_t V, int fused_relu, void *ws,
+                       size_t ws_bytes, dlm_precision prec, void *stream) {
+  dlm_status s = lsc_check(p, C, O, V, prec);
+  if (s != DLM_OK) return s;
+  if (!ws) return fail(DLM_EINVAL, "workspace is NULL");
+  if (fused_relu && !a_out && V > 0) return fail(DLM_EINVAL, "fused_relu needs the forward output a_out");
+  const int T = p->T, m = int(p->m);
+  const int64_t P = p->m * T;
+  if (V == 0) {
+    if (dW || dbias) {
+      LscWs w0 = lsc_ws_carve(p, C, O, 1, ws);
+      if (ws_bytes < lsc_ws_need(p, C, O, 1)) return fail(DLM_EWORKSPACE, "workspace too small");
+      if (dW && (s = launched(launch_reduce_weight_partials(w0.part, 0, dW, dbias, C, O, T, 0, stream))) != DLM_OK)
+        return s;
+      if (!dW && dbias) return fail(DLM_EINVAL, "dbias without dW is not supported");
+    }
+    return ok();
+  }
+  if (!a_in || !W || !da_out) return fail(DLM_EINVAL, "null device pointer");
+  if (dbias && !dW) return fail(DLM_EINVAL, "dbias without dW is not supported");
+  const int64_t Vc = lsc_chunk(p, C, O, V, ws_bytes);
+  if (Vc == 0)
+    return fail(DLM_EWORKSPACE, "workspace of %zu bytes is below the %zu-byte minimum", ws_bytes,
+                lsc_ws_need(p, C, O, std::min<int64_t>(V, kMinChunk)));
+  LscWs w = lsc_ws_carve(p, C, O, Vc, ws);
+  if ((s = launched(launch_prepare_weights(W, w.Wt, w.Wh, w.Wth, C, O, T, stream))) != DLM_OK) return s;
+  for (int64_t v0 = 0; v0 < V; v0 += Vc) {
+    const int64_t nv = std::min(Vc, V - v0);
+    TableGemm rb;  // dy[(v,o)][i] = sum_k P_m[k][i] (da * [a_out > 0])[(v,o)][k]
+    rb.A = da_out + v0 * O * p->K_out;
+    rb.mask = fused_relu ? a_out + v0 * O * p->K_out : nullptr;
+    rb.lda = p->K_out;
+    rb.Bf = p->dPmT.f32;
+    rb.Bh = p->dPmT.bf16;
+    rb.C = w.y;
+    rb.ldc = m;
+    rb.M = nv * O;
+    rb.N = m;
+    rb.K = p->K_out;
+    if ((s = launched(launch_table_gemm(rb, prec, stream))) != DLM_OK) return s;
+    if (dW) {
+      TableGemm rs;  // recompute the neighbourhood matrices X
+      rs.A = a_in + v0 * C * p->K_in;
+      rs.lda = p->K_in;
+      rs.Bf = p->dBnb.f32;
+      rs.Bh = p->dBnb.bf16;
+      rs.C = w.X;
+      rs.ldc = P;
+      rs.M = nv * C;
+      rs.N = int(P);
+      rs.K = p->K_in;
+      if ((s = launched(launch_table_gemm(rs, prec, stream))) != DLM_OK) return s;
+      const int splits = lsc_weight_splits(nv, m, kWeightSplitTarget);
+      if ((s = launched(launch_lsc_contract_bwd_weight(w.X, w.y, w.part, nv, C, O, m, T, splits, prec, stream))) !=
+          DLM_OK)
+        return s;
+      if ((s = launched(launch_reduce_weight_partials(w.part, splits, dW, dbias, C, O, T, v0 > 0, stream))) != DLM_OK)
+        return s;
+    }
+    if (da_in) {
+      if ((s = launched(launch_lsc_contract_bwd_data(w.y, w.Wt, w.Wth, w.X, nv, C, O, m, T, prec, stream))) != DLM_OK)
+        return s;
+      TableGemm ra;  // da[(v,c)][j] = sum_p B_nb[p][j] dX[(v,c)][p]
+      ra.A = w.X;
+      ra.lda = P;
+      ra.Bf = p->dBnbT.f32;
+      ra.Bh = p->dBnbT.bf16;
+      ra.C = da_in + v0 * C * p->K_in;
+      ra.ldc = p->K_in;
+      ra.M = nv * C;
+      ra.N = p->K_in;
+      ra.K = int(P);
+      if ((s = launched(launch_table_gemm(ra, prec, stream))) != DLM_OK) return s;
+    }
+  }
+  return ok();
+}
+
+// ----------------------------------------------------------------- training
+size_t dlm_mse_workspace_bytes(int64_t n) { return align256(size_t(mse_blocks(std::max<int64_t>(n, 1))) * 4); }
+
+dlm_status dlm_mse_fwd_bwd(const float *pred, const float *target, int64_t n, float *loss, float *dpred, void *ws,
+                           size_t ws_bytes, void *stream) {
+  if (n <= 0) return fail(DLM_EINVAL, "n must be > 0");
+  if (!pred || !target || !loss || !ws) return fail(DLM_EINVAL, "null device pointer");
+  if (ws_bytes < dlm_mse_workspace_bytes(n)) return fail(DLM_EWORKSPACE, "workspace too small");
+  const int nb = mse_blocks(n);
+  dlm_status s = launched(launch_mse(pred, target, n, loss, dpred, static_cast<float *>(ws), nb, stream));
+  return s == DLM_OK ? ok() : s;
+}
+
+dlm_status dlm_adam_step(float *w, const float *g, float *m, float *v, int64_t n, float lr, float beta1, float beta2,
+                         float eps, int64_t step, void *stream) {
+  if (n < 0) return fail(DLM_EINVAL, "n must be >= 0");
+  if (n == 0) return ok();
+  if (!w || !g || !m || !v) return fail(DLM_EINVAL, "null device pointer");
+  if (step < 1) return fail(DLM_EINVAL, "step is 1-based");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f)) return fail(DLM_EINVAL, "betas must be in [0,1)");
+  const float c1 = float(1.0 - std::pow(double(beta1), double(step)));
+  const float c2 = float(1.0 - std::pow(double(beta2), double(step)));
+  dlm_status s = launched(launch_adam(w, g, m, v, n, lr, beta1, beta2, eps, c1, c2, stream));
+  return s == DLM_OK ? ok() : s;
+}
+
+}  // extern "C"

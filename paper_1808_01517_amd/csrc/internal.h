@@ -1,0 +1,79 @@
+// Internal declarations of libdelimit (not part of the public ABI).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/delimit.h"
+
+namespace dlm {
+
+constexpr int kMaxShOrder = 16;
+constexpr int kMaxChannels = 256;
+constexpr int kMaxTaps = 256;
+
+// ---------------------------------------------------------------- host fp64
+int sh_num_coeffs(int L);
+bool sh_order_ok(int L);
+bool unit_dir(const double *in, double *out);
+void sh_row(int L, const double *u, double *row);
+void sh_basis_unit(int L, const double *u, int64_t n, double *B);
+bool fit_from_basis(int L, const double *B, int64_t n, double lambda, double *P);
+void group_shells(const double *bvals, int64_t n, double b0_max, double rel_tol,
+                  std::vector<std::vector<int64_t>> &members, std::vector<double> &centres);
+void kernel_points_unit(const double *g, int64_t m, const int *ks, int R, double alpha, double *pts);
+uint16_t f32_to_bf16_rne(float f);
+uint16_t f64_to_bf16_rne(double d);
+
+// ------------------------------------------------------------ device tables
+// A row-major matrix [rows][cols] uploaded once as float32 and bfloat16.
+struct DevMat {
+  int rows = 0, cols = 0;
+  float *f32 = nullptr;
+  uint16_t *bf16 = nullptr;
+};
+
+// ------------------------------------------------------------------ kernels
+// C[r][n] = sum_k A[r][k] * B[n][k] over one group g:
+//   A row r of group g at A + r*lda + g*a_gs, mask (same indexing) optional:
+//     A is replaced by A * (mask > 0);
+//   B (float32 or bf16 table, [N][K] row-major) at B + g*b_gs;
+//   C at C + r*ldc + g*c_gs, optional ReLU.
+struct TableGemm {
+  const float *A = nullptr;
+  const float *mask = nullptr;
+  int64_t lda = 0, a_gs = 0;
+  const float *Bf = nullptr;
+  const uint16_t *Bh = nullptr;
+  int64_t b_gs = 0;
+  float *C = nullptr;
+  int64_t ldc = 0, c_gs = 0;
+  int64_t M = 0;
+  int N = 0, K = 0, groups = 1;
+  int relu = 0;
+};
+int launch_table_gemm(const TableGemm &g, dlm_precision prec, void *stream);
+
+// y[v][o][i] = bias[o] + sum_{c,t} W[o][c][t] X[v][c][i*T+t]
+int launch_lsc_contract_fwd(const float *X, const float *W, const uint16_t *Wh, const float *bias, float *y,
+                            int64_t V, int C, int O, int m, int T, dlm_precision prec, void *stream);
+// dX[v][c][i*T+t] = sum_o W[o][c][t] dy[v][o][i]   (Wt = W transposed [C*T][O])
+int launch_lsc_contract_bwd_data(const float *dy, const float *Wt, const uint16_t *Wth, float *dX, int64_t V,
+                                 int C, int O, int m, int T, dlm_precision prec, void *stream);
+// partial[s][(c*T+t)][o] and partial[s][C*T][o] (bias row) over voxel split s.
+int launch_lsc_contract_bwd_weight(const float *X, const float *dy, float *partial, int64_t V, int C, int O, int m,
+                                   int T, int splits, dlm_precision prec, void *stream);
+// dW[o][c][t] (+)= sum_s partial[s][c*T+t][o]; db[o] (+)= sum_s partial[s][C*T][o]
+int launch_reduce_weight_partials(const float *partial, int splits, float *dW, float *db, int C, int O, int T,
+                                  int accumulate, void *stream);
+// Wt[(c*T+t)][o] = W[o][c][t] (+ bf16 copies of W and Wt when requested)
+int launch_prepare_weights(const float *W, float *Wt, uint16_t *Wh, uint16_t *Wth, int C, int O, int T,
+                           void *stream);
+int launch_mse(const float *pred, const float *target, int64_t n, float *loss, float *dpred, float *partials,
+               int nblocks, void *stream);
+int mse_blocks(int64_t n);
+int launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
+                float c1, float c2, void *stream);
+
+}  // namespace dlm

@@ -1,0 +1,586 @@
+// HIP kernels for gfx950 (MI355X): every contraction of the DELIMIT layers
+// runs through one matrix-core GEMM core whose operand addressing is a
+// policy type, so the SH transforms (Sec. 2.2), the LSC neighbourhood
+// resampling, the cyclic-kernel row dot and the refit (Sec. 2.3) and all
+// their adjoints share the same tiled MFMA pipeline:
+//
+//   C[r][n] = sum_k A(r, k) * B(n, k)
+//
+// FP32 form: v_mfma_f32_16x16x4_f32 (float32 products and accumulation).
+// BF16 form: v_mfma_f32_16x16x32_bf16 with operands rounded to bfloat16
+// (round to nearest even) as they are staged into LDS, float32 accumulation.
+//
+// Block = 256 threads (4 wave64s).  A block computes a BM x BN tile; each
+// wave owns TM x TN MFMA tiles of 16 x 16.  K is walked in BK slices staged
+// through LDS with the next slice prefetched into registers while the
+// current one is multiplied.  Ragged M/N/K are zero-filled at load and
+// masked at store.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "internal.h"
+
+namespace dlm {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint16_t to_bf16_bits(float f) {
+  __bf16 h = (__bf16)f;  // hardware round-to-nearest-even conversion
+  return __builtin_bit_cast(uint16_t, h);
+}
+
+template <int BM_, int BN_, int WAVES_M_, int WAVES_N_>
+struct Cfg {
+  static constexpr int BM = BM_, BN = BN_, WM = WAVES_M_, WN = WAVES_N_;
+  static constexpr int TM = BM / (WM * 16), TN = BN / (WN * 16);
+  static_assert(WM * WN == 4, "four waves per block");
+  static_assert(TM * WM * 16 == BM && TN * WN * 16 == BN, "tile shape");
+};
+using CfgSquare = Cfg<64, 64, 2, 2>;   // general
+using CfgNarrow = Cfg<64, 48, 4, 1>;   // N = 45 / 90 style outputs
+using CfgThin = Cfg<128, 16, 4, 1>;    // N <= 16
+
+// ------------------------------------------------------------- FP32 core
+template <class CF, class AL, class BL, class CS>
+__global__ __launch_bounds__(256) void gemm_f32_kernel(AL al, BL bl, CS cs, int64_t M, int N, int K, int ksplit) {
+  constexpr int BM = CF::BM, BN = CF::BN, BK = 16;
+  constexpr int APT = BM * BK / 256, BPT = BN * BK / 256;
+  __shared__ float As[BK][BM + 4];
+  __shared__ float Bs[BK][BN + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % CF::WM, wn = wave / CF::WM;
+  const int64_t m0 = (int64_t)blockIdx.x * BM;
+  const int n0 = blockIdx.y * BN;
+  const int g = blockIdx.z;
+  int kbeg = 0, kend = K;
+  if (ksplit > 0) {
+    kbeg = g * ksplit;
+    kend = min(K, kbeg + ksplit);
+  }
+  float ra[APT], rb[BPT];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < APT; ++p) {
+      const int e = tid + p * 256;
+      int mm, kk;
+      if constexpr (AL::kContig) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
+      const int64_t r = m0 + mm;
+      const int k = k0 + kk;
+      ra[p] = (r < M && k < kend) ? al(r, k, g) : 0.0f;
+    }
+#pragma unroll
+    for (int p = 0; p < BPT; ++p) {
+      const int e = tid + p * 256;
+      int nn, kk;
+      if constexpr (BL::kContig) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
+      const int n = n0 + nn;
+      const int k = k0 + kk;
+      rb[p] = (n < N && k < kend) ? bl(n, k, g) : 0.0f;
+    }
+  };
+  floatx4 acc[CF::TM][CF::TN];
+#pragma unroll
+  for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < CF::TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+    for (int p = 0; p < APT; ++p) {
+      const int e = tid + p * 256;
+      int mm, kk;
+      if constexpr (AL::kContig) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
+      As[kk][mm] = ra[p];
+    }
+#pragma unroll
+    for (int p = 0; p < BPT; ++p) {
+      const int e = tid + p * 256;
+      int nn, kk;
+      if constexpr (BL::kContig) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
+      Bs[kk][nn] = rb[p];
+    }
+    __syncthreads();
+    if (k0 + BK < kend) load(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      float a[CF::TM], b[CF::TN];
+#pragma unroll
+      for (int i = 0; i < CF::TM; ++i) a[i] = As[kk + (lane >> 4)][(wm * CF::TM + i) * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < CF::TN; ++j) b[j] = Bs[kk + (lane >> 4)][(wn * CF::TN + j) * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < CF::TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < CF::TN; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = m0 + (wm * CF::TM + i) * 16 + 4 * (lane >> 4) + q;
+        const int n = n0 + (wn * CF::TN + j) * 16 + (lane & 15);
+        if (r < M && n < N) cs(r, n, g, acc[i][j][q]);
+      }
+}
+
+// ------------------------------------------------------------- BF16 core
+template <class CF, class AL, class BL, class CS>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int64_t M, int N, int K, int ksplit) {
+  constexpr int BM = CF::BM, BN = CF::BN, BK = 32, LD = BK + 8;
+  constexpr int APT = BM * BK / 256, BPT = BN * BK / 256;
+  __shared__ __attribute__((aligned(16))) uint16_t As[BM * LD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % CF::WM, wn = wave / CF::WM;
+  const int64_t m0 = (int64_t)blockIdx.x * BM;
+  const int n0 = blockIdx.y * BN;
+  const int g = blockIdx.z;
+  int kbeg = 0, kend = K;
+  if (ksplit > 0) {
+    kbeg = g * ksplit;
+    kend = min(K, kbeg + ksplit);
+  }
+  uint16_t ra[APT], rb[BPT];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < APT; ++p) {
+      const int e = tid + p * 256;
+      int mm, kk;
+      if constexpr (AL::kContig) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
+      const int64_t r = m0 + mm;
+      const int k = k0 + kk;
+      ra[p] = (r < M && k < kend) ? to_bf16_bits(al(r, k, g)) : uint16_t(0);
+    }
+#pragma unroll
+    for (int p = 0; p < BPT; ++p) {
+      const int e = tid + p * 256;
+      int nn, kk;
+      if constexpr (BL::kContig) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
+      const int n = n0 + nn;
+      const int k = k0 + kk;
+      if constexpr (std::is_same<typename BL::type, float>::value)
+        rb[p] = (n < N && k < kend) ? to_bf16_bits(bl(n, k, g)) : uint16_t(0);
+      else
+        rb[p] = (n < N && k < kend) ? bl(n, k, g) : uint16_t(0);
+    }
+  };
+  floatx4 acc[CF::TM][CF::TN];
+#pragma unroll
+  for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < CF::TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+    for (int p = 0; p < APT; ++p) {
+      const int e = tid + p * 256;
+      int mm, kk;
+      if constexpr (AL::kContig) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
+      As[mm * LD + kk] = ra[p];
+    }
+#pragma unroll
+    for (int p = 0; p < BPT; ++p) {
+      const int e = tid + p * 256;
+      int nn, kk;
+      if constexpr (BL::kContig) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
+      Bs[nn * LD + kk] = rb[p];
+    }
+    __syncthreads();
+    if (k0 + BK < kend) load(k0 + BK);
+    bf16x8 a[CF::TM], b[CF::TN];
+#pragma unroll
+    for (int i = 0; i < CF::TM; ++i)
+      a[i] = *reinterpret_cast<const bf16x8 *>(&As[((wm * CF::TM + i) * 16 + (lane & 15)) * LD + 8 * (lane >> 4)]);
+#pragma unroll
+    for (int j = 0; j < CF::TN; ++j)
+      b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[((wn * CF::TN + j) * 16 + (lane & 15)) * LD + 8 * (lane >> 4)]);
+#pragma unroll
+    for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < CF::TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < CF::TN; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = m0 + (wm * CF::TM + i) * 16 + 4 * (lane >> 4) + q;
+        const int n = n0 + (wn * CF::TN + j) * 16 + (lane & 15);
+        if (r < M && n < N) cs(r, n, g, acc[i][j][q]);
+      }
+}
+
+// ------------------------------------------------------------- launching
+template <class CF>
+static dim3 grid_for(int64_t M, int N, int Z) {
+  return dim3((unsigned)((M + CF::BM - 1) / CF::BM), (unsigned)((N + CF::BN - 1) / CF::BN), (unsigned)Z);
+}
+
+enum class Shape { Square, Narrow, Thin };
+
+static Shape pick_shape(int N) {
+  if (N <= 16) return Shape::Thin;
+  const int p48 = (N + 47) / 48 * 48, p64 = (N + 63) / 64 * 64;
+  return p48 < p64 ? Shape::Narrow : Shape::Square;
+}
+
+static int rows_per_block(Shape s) { return s == Shape::Thin ? 128 : 64; }
+
+template <class AL, class BL, class CS>
+static int run_gemm(AL al, BL bl, CS cs, int64_t M, int N, int K, int Z, int ksplit, dlm_precision prec,
+                    hipStream_t st, Shape shape) {
+  if (M <= 0 || N <= 0 || Z <= 0) return 0;
+#define DLM_LAUNCH(CFG)                                                                                   \
+  do {                                                                                                    \
+    dim3 grid = grid_for<CFG>(M, N, Z);                                                                   \
+    if (prec == DLM_BF16)                                                                                 \
+      hipLaunchKernelGGL((gemm_bf16_kernel<CFG, AL, BL, CS>), grid, dim3(256), 0, st, al, bl, cs, M, N, K, \
+                         ksplit);                                                                         \
+    else                                                                                                  \
+      hipLaunchKernelGGL((gemm_f32_kernel<CFG, AL, BL, CS>), grid, dim3(256), 0, st, al, bl, cs, M, N, K,  \
+                         ksplit);                                                                         \
+  } while (0)
+  switch (shape) {
+    case Shape::Thin: DLM_LAUNCH(CfgThin); break;
+    case Shape::Narrow: DLM_LAUNCH(CfgNarrow); break;
+    default: DLM_LAUNCH(CfgSquare); break;
+  }
+#undef DLM_LAUNCH
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ------------------------------------------------------- operand policies
+template <bool MASK>
+struct ARowMajor {
+  static constexpr bool kContig = true;
+  const float *A, *mask;
+  int64_t lda, gs;
+  __device__ float operator()(int64_t r, int k, int g) const {
+    const int64_t o = r * lda + (int64_t)g * gs + k;
+    float v = A[o];
+    if constexpr (MASK) v = mask[o] > 0.0f ? v : 0.0f;
+    return v;
+  }
+};
+
+struct BTableF {
+  static constexpr bool kContig = true;
+  using type = float;
+  const float *B;
+  int64_t gs;
+  int K;
+  __device__ float operator()(int n, int k, int g) const { return B[(int64_t)g * gs + (int64_t)n * K + k]; }
+};
+
+struct BTableH {
+  static constexpr bool kContig = true;
+  using type = uint16_t;
+  const uint16_t *B;
+  int64_t gs;
+  int K;
+  __device__ uint16_t operator()(int n, int k, int g) const { return B[(int64_t)g * gs + (int64_t)n * K + k]; }
+};
+
+struct CRowMajor {
+  float *C;
+  int64_t ldc, gs;
+  int relu;
+  __device__ void operator()(int64_t r, int n, int g, float v) const {
+    if (relu) v = fmaxf(v, 0.0f);
+    C[r * ldc + (int64_t)g * gs + n] = v;
+  }
+};
+
+int launch_table_gemm(const TableGemm &t, dlm_precision prec, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const Shape sh = pick_shape(t.N);
+  CRowMajor cs{t.C, t.ldc, t.c_gs, t.relu};
+  if (prec == DLM_BF16) {
+    BTableH bl{t.Bh, t.b_gs, t.K};
+    if (t.mask) return run_gemm(ARowMajor<true>{t.A, t.mask, t.lda, t.a_gs}, bl, cs, t.M, t.N, t.K, t.groups, 0, prec, st, sh);
+    return run_gemm(ARowMajor<false>{t.A, nullptr, t.lda, t.a_gs}, bl, cs, t.M, t.N, t.K, t.groups, 0, prec, st, sh);
+  }
+  BTableF bl{t.Bf, t.b_gs, t.K};
+  if (t.mask) return run_gemm(ARowMajor<true>{t.A, t.mask, t.lda, t.a_gs}, bl, cs, t.M, t.N, t.K, t.groups, 0, prec, st, sh);
+  return run_gemm(ARowMajor<false>{t.A, nullptr, t.lda, t.a_gs}, bl, cs, t.M, t.N, t.K, t.groups, 0, prec, st, sh);
+}
+
+// --------------------------------------------- LSC neighbourhood contraction
+// Row r = (v, i) of the neighbourhood matrix; column k = (c, t).
+struct ANbhd {
+  static constexpr bool kContig = true;
+  const float *X;
+  int m, T, C;
+  __device__ float operator()(int64_t r, int k, int) const {
+    const int64_t v = r / m;
+    const int i = (int)(r - v * m);
+    const int c = k / T, t = k - c * T;
+    const int64_t P = (int64_t)m * T;
+    return X[(v * C + c) * P + (int64_t)i * T + t];
+  }
+};
+
+struct BWeightF {
+  static constexpr bool kContig = true;
+  using type = float;
+  const float *W;
+  int ld;
+  __device__ float operator()(int n, int k, int) const { return W[(int64_t)n * ld + k]; }
+};
+
+struct BWeightH {
+  static constexpr bool kContig = true;
+  using type = uint16_t;
+  const uint16_t *W;
+  int ld;
+  __device__ uint16_t operator()(int n, int k, int) const { return W[(int64_t)n * ld + k]; }
+};
+
+struct CSignalY {
+  float *y;
+  const float *bias;
+  int m, O;
+  __device__ void operator()(int64_t r, int o, int, float v) const {
+    const int64_t vx = r / m;
+    const int i = (int)(r - vx * m);
+    if (bias) v += bias[o];
+    y[(vx * O + o) * m + i] = v;
+  }
+};
+
+int launch_lsc_contract_fwd(const float *X, const float *W, const uint16_t *Wh, const float *bias, float *y,
+                            int64_t V, int C, int O, int m, int T, dlm_precision prec, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t M = V * m;
+  const int K = C * T;
+  ANbhd al{X, m, T, C};
+  CSignalY cs{y, bias, m, O};
+  const Shape sh = pick_shape(O);
+  if (prec == DLM_BF16) return run_gemm(al, BWeightH{Wh, K}, cs, M, O, K, 1, 0, prec, st, sh);
+  return run_gemm(al, BWeightF{W, K}, cs, M, O, K, 1, 0, prec, st, sh);
+}
+
+// dy as the A operand: row r = (v, i), column k = o; consecutive rows are
+// consecutive in memory.
+struct ADy {
+  static constexpr bool kContig = false;
+  const float *dy;
+  int m, O;
+  __device__ float operator()(int64_t r, int o, int) const {
+    const int64_t v = r / m;
+    const int i = (int)(r - v * m);
+    return dy[(v * O + o) * m + i];
+  }
+};
+
+struct CNbhd {
+  float *dX;
+  int m, T, C;
+  __device__ void operator()(int64_t r, int n, int, float val) const {
+    const int64_t v = r / m;
+    const int i = (int)(r - v * m);
+    const int c = n / T, t = n - c * T;
+    const int64_t P = (int64_t)m * T;
+    dX[(v * C + c) * P + (int64_t)i * T + t] = val;
+  }
+};
+
+int launch_lsc_contract_bwd_data(const float *dy, const float *Wt, const uint16_t *Wth, float *dX, int64_t V, int C,
+                                 int O, int m, int T, dlm_precision prec, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t M = V * m;
+  const int N = C * T;
+  ADy al{dy, m, O};
+  CNbhd cs{dX, m, T, C};
+  const Shape sh = pick_shape(N);
+  if (prec == DLM_BF16) return run_gemm(al, BWeightH{Wth, O}, cs, M, N, O, 1, 0, prec, st, sh);
+  return run_gemm(al, BWeightF{Wt, O}, cs, M, N, O, 1, 0, prec, st, sh);
+}
+
+// Weight gradient: rows r = (c, t) plus one bias row (r = C*T, value 1),
+// columns n = o, reduction k = (v, i) split into `splits` slices.
+struct AXt {
+  static constexpr bool kContig = false;
+  const float *X;
+  int m, T, C;
+  __device__ float operator()(int64_t r, int k, int) const {
+    const int CT = C * T;
+    if (r == CT) return 1.0f;
+    const int v = k / m, i = k - v * m;
+    const int c = (int)r / T, t = (int)r - c * T;
+    const int64_t P = (int64_t)m * T;
+    return X[((int64_t)v * C + c) * P + (int64_t)i * T + t];
+  }
+};
+
+struct BDyT {
+  static constexpr bool kContig = true;
+  using type = float;
+  const float *dy;
+  int m, O;
+  __device__ float operator()(int o, int k, int) const {
+    const int v = k / m, i = k - v * m;
+    return dy[((int64_t)v * O + o) * m + i];
+  }
+};
+
+struct CPartial {
+  float *part;
+  int rows, O;
+  __device__ void operator()(int64_t r, int o, int s, float v) const {
+    part[((int64_t)s * rows + r) * O + o] = v;
+  }
+};
+
+int launch_lsc_contract_bwd_weight(const float *X, const float *dy, float *partial, int64_t V, int C, int O, int m,
+                                   int T, int splits, dlm_precision prec, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int rows = C * T + 1;
+  const int64_t Kfull = V * m;
+  const int bk = 32;  // a multiple of both cores' K slice
+  int ksplit = (int)((Kfull + splits - 1) / splits);
+  ksplit = (ksplit + bk - 1) / bk * bk;
+  const int used = (int)((Kfull + ksplit - 1) / ksplit);
+  // splits beyond `used` would see an empty range; the caller sizes `splits`
+  // so that every slice is non-empty and reduces exactly `splits` partials.
+  if (used != splits) return -2;
+  return run_gemm(AXt{X, m, T, C}, BDyT{dy, m, O}, CPartial{partial, rows, O}, rows, O, (int)Kfull, splits, ksplit,
+                  prec, st, pick_shape(O));
+}
+
+int lsc_weight_splits(int64_t V, int m, int target) {
+  const int64_t Kfull = V * m;
+  const int bk = 32;
+  int s = target;
+  while (s > 1) {
+    int ksplit = (int)((Kfull + s - 1) / s);
+    ksplit = (ksplit + bk - 1) / bk * bk;
+    if ((Kfull + ksplit - 1) / ksplit == s) break;
+    --s;
+  }
+  return s < 1 ? 1 : s;
+}
+
+// --------------------------------------------------------- small kernels
+__global__ void reduce_weight_partials_kernel(const float *part, int splits, float *dW, float *db, int C, int O,
+                                              int T, int accumulate) {
+  const int CT = C * T, rows = CT + 1;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * O) return;
+  const int r = idx / O, o = idx - r * O;
+  float s = 0.0f;
+  for (int p = 0; p < splits; ++p) s += part[((int64_t)p * rows + r) * O + o];
+  if (r < CT) {
+    float *dst = dW + (int64_t)o * CT + r;
+    *dst = accumulate ? *dst + s : s;
+  } else if (db) {
+    db[o] = accumulate ? db[o] + s : s;
+  }
+}
+
+int launch_reduce_weight_partials(const float *partial, int splits, float *dW, float *db, int C, int O, int T,
+                                  int accumulate, void *stream) {
+  const int n = (C * T + 1) * O;
+  hipLaunchKernelGGL(reduce_weight_partials_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                     partial, splits, dW, db, C, O, T, accumulate);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+__global__ void prepare_weights_kernel(const float *W, float *Wt, uint16_t *Wh, uint16_t *Wth, int C, int O, int T) {
+  const int CT = C * T;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= O * CT) return;
+  const int o = idx / CT, ct = idx - o * CT;
+  const float w = W[idx];
+  Wt[(int64_t)ct * O + o] = w;
+  if (Wh) Wh[idx] = to_bf16_bits(w);
+  if (Wth) Wth[(int64_t)ct * O + o] = to_bf16_bits(w);
+}
+
+int launch_prepare_weights(const float *W, float *Wt, uint16_t *Wh, uint16_t *Wth, int C, int O, int T,
+                           void *stream) {
+  const int n = O * C * T;
+  hipLaunchKernelGGL(prepare_weights_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, W, Wt, Wh,
+                     Wth, C, O, T);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// MSE: each block sums its grid-stride share in a fixed order and writes one
+// partial; a single block then adds the partials in index order.
+__global__ __launch_bounds__(256) void mse_partial_kernel(const float *pred, const float *target, int64_t n,
+                                                          float *dpred, float *partials, float scale) {
+  __shared__ float red[256];
+  float s = 0.0f;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const float d = pred[i] - target[i];
+    s += d * d;
+    if (dpred) dpred[i] = scale * d;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void mse_final_kernel(const float *partials, int nb, float *loss, float inv_n) {
+  __shared__ float red[256];
+  float s = 0.0f;
+  for (int i = threadIdx.x; i < nb; i += 256) s += partials[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = red[0] * inv_n;
+}
+
+int mse_blocks(int64_t n) {
+  int64_t b = (n + 256 * 8 - 1) / (256 * 8);
+  if (b < 1) b = 1;
+  if (b > 2048) b = 2048;
+  return (int)b;
+}
+
+int launch_mse(const float *pred, const float *target, int64_t n, float *loss, float *dpred, float *partials,
+               int nblocks, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(mse_partial_kernel, dim3(nblocks), dim3(256), 0, st, pred, target, n, dpred, partials,
+                     (float)(2.0 / (double)n));
+  hipLaunchKernelGGL(mse_final_kernel, dim3(1), dim3(256), 0, st, partials, nblocks, loss, (float)(1.0 / (double)n));
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+__global__ void adam_kernel(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
+                            float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+int launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
+                float c1, float c2, void *stream) {
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, w, g, m, v,
+                     n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace dlm

@@ -1,0 +1,199 @@
+"""GPU parity of the HIP layers against the FP64 oracle.
+
+Norm-wise relative error ||out - ref||_F / ||ref||_F per output tensor:
+FP32 form <= 1e-5, BF16 form <= 2e-2 (the tolerances the workloads state).
+Sizes span several tiles with ragged tails (V not a multiple of any tile).
+"""
+import numpy as np
+import pytest
+import torch
+
+import datagen as dg
+import paper_1808_01517_amd as dl
+from oracle import lsc as olsc
+from oracle import sh as osh
+from oracle import stack as ostack
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "bf16": 2e-2}
+DEV = "cuda:0"
+
+
+def rel(out, ref):
+    out = out.detach().double().cpu().numpy() if isinstance(out, torch.Tensor) else np.asarray(out, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.linalg.norm(out - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+@pytest.fixture(scope="module")
+def c2_acq():
+    return dg.make_acquisition(dg.C2.config, dg.C2.shell_b, dg.C2.dirs_per_shell, dg.C2.perturb_deg, dg.C2.n_b0)
+
+
+@pytest.fixture(scope="module")
+def c1_acq():
+    return dg.make_acquisition(dg.C1.config, dg.C1.shell_b, dg.C1.dirs_per_shell, dg.C1.perturb_deg, dg.C1.n_b0)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("which", ["c1", "c2"])
+def test_sh_transforms(prec, which, c1_acq, c2_acq):
+    acq, L, V = (c1_acq, 4, 4096 + 37) if which == "c1" else (c2_acq, 8, 3000 + 13)
+    oplan = osh.SHPlan(acq.bvecs, acq.bvals, L, 0.006)
+    plan = dl.SHPlan(acq.bvecs, acq.bvals, L, 0.006)
+    assert plan.n_shells == oplan.n_shells and plan.K == oplan.K
+    batch = dg.stick_ball_batch(acq, V, 3, 20.0, dg.rng_for(11, 2, 0))
+    x = batch.x
+    xg = cuda(x)
+    c = dl.signal2sh_fwd(plan, xg, precision=prec)
+    c_ref = osh.signal2sh(oplan, x.astype(np.float32).astype(np.float64))
+    assert rel(c, c_ref) <= TOL[prec]
+    xr = dl.sh2signal_fwd(plan, c, precision=prec)
+    xr_ref = osh.sh2signal(oplan, c.double().cpu().numpy())
+    assert rel(xr, xr_ref) <= TOL[prec]
+    rng = np.random.default_rng(3)
+    dc = rng.standard_normal(c_ref.shape)
+    dx = dl.signal2sh_bwd(plan, cuda(dc), precision=prec)
+    assert rel(dx, osh.signal2sh_adjoint(oplan, dc.astype(np.float32))) <= TOL[prec]
+    dxx = rng.standard_normal(x.shape)
+    dcc = dl.sh2signal_bwd(plan, cuda(dxx), precision=prec)
+    assert rel(dcc, osh.sh2signal_adjoint(oplan, dxx.astype(np.float32))) <= TOL[prec]
+
+
+def _lsc_case(C, O, L_in, L_out, ks, m_dirs, V, seed):
+    g = dg.fibonacci_hemisphere(m_dirs)
+    oplan = olsc.LSCPlan(g, L_in, L_out, ks, np.deg2rad(30), 0.006)
+    plan = dl.LSCPlan(g, L_in, L_out, ks, np.deg2rad(30), 0.006)
+    W, b = dg.lsc_weights(seed, 0, C, O, plan.T)
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((V, C, plan.K_in)).astype(np.float32).astype(np.float64)
+    return oplan, plan, W.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64), a
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("case", [
+    (1, 8, 4, 4, (6, 6), 30, 517),
+    (3, 32, 8, 8, (8, 8), 90, 203),
+    (32, 3, 8, 8, (8, 8), 90, 203),
+    (3, 5, 4, 8, (8, 8), 90, 131),
+])
+@pytest.mark.parametrize("relu", [False, True])
+def test_lsc_forward_backward(prec, case, relu):
+    C, O, L_in, L_out, ks, m, V = case
+    oplan, plan, W, b, a = _lsc_case(C, O, L_in, L_out, ks, m, V, 5)
+    out_ref, z = olsc.lsc_forward(oplan, a, W, b, relu)
+    ag, Wg, bg = cuda(a), cuda(W), cuda(b)
+    out = dl.lsc_fwd(plan, ag, Wg, bg, relu=relu, precision=prec)
+    assert rel(out, out_ref) <= TOL[prec]
+    da_out = np.random.default_rng(9).standard_normal(out_ref.shape).astype(np.float32).astype(np.float64)
+    # mask from the GPU's own forward output so both sides use the same ReLU pattern
+    z_mask = out.double().cpu().numpy() if relu else z
+    da_ref, dW_ref, db_ref = olsc.lsc_backward(oplan, a, W, z_mask, da_out, relu)
+    da, dW, db = dl.lsc_bwd(plan, ag, Wg, cuda(da_out), a_out=out, relu=relu, precision=prec)
+    assert rel(da, da_ref) <= TOL[prec]
+    assert rel(dW, dW_ref) <= TOL[prec]
+    assert rel(db, db_ref) <= TOL[prec]
+
+
+def test_lsc_chunked_workspace_matches_single_pass():
+    # a workspace for 64 voxels forces several passes; results must agree with one pass
+    C, O = 3, 32
+    oplan, plan, W, b, a = _lsc_case(C, O, 8, 8, (8, 8), 90, 333, 7)
+    ag, Wg, bg = cuda(a), cuda(W), cuda(b)
+    small = dl.Workspace(dl.lsc_workspace_bytes(plan, C, O, 64), DEV)
+    big = dl.Workspace(dl.lsc_workspace_bytes(plan, C, O, 333), DEV)
+    o1 = dl.lsc_fwd(plan, ag, Wg, bg, relu=True, workspace=small)
+    o2 = dl.lsc_fwd(plan, ag, Wg, bg, relu=True, workspace=big)
+    assert torch.equal(o1, o2)
+    g = cuda(np.random.default_rng(1).standard_normal(o1.shape))
+    r1 = dl.lsc_bwd(plan, ag, Wg, g, a_out=o1, relu=True, workspace=small)
+    r2 = dl.lsc_bwd(plan, ag, Wg, g, a_out=o2, relu=True, workspace=big)
+    assert torch.equal(r1[0], r2[0])
+    assert rel(r1[1], r2[1].double().cpu().numpy()) < 1e-6
+    ref = olsc.lsc_backward(oplan, a, W, o1.double().cpu().numpy(), g.double().cpu().numpy(), True)
+    assert rel(r1[1], ref[1]) <= 1e-5 and rel(r1[2], ref[2]) <= 1e-5
+
+
+def test_lsc_deterministic():
+    C, O = 32, 3
+    _, plan, W, b, a = _lsc_case(C, O, 8, 8, (8, 8), 90, 257, 8)
+    ag, Wg = cuda(a), cuda(W)
+    g = cuda(np.random.default_rng(2).standard_normal((257, O, 45)))
+    r1 = dl.lsc_bwd(plan, ag, Wg, g)
+    r2 = dl.lsc_bwd(plan, ag, Wg, g)
+    for x, y in zip(r1, r2):
+        assert torch.equal(x, y)
+
+
+def test_mse_and_adam():
+    rng = np.random.default_rng(4)
+    p = rng.standard_normal(10007)
+    t = rng.standard_normal(10007)
+    loss, dp = dl.mse_fwd_bwd(cuda(p), cuda(t))
+    l_ref, g_ref = ostack.mse(p.astype(np.float32).astype(np.float64), t.astype(np.float32).astype(np.float64))
+    assert abs(loss.item() - l_ref) / l_ref < 1e-5
+    assert rel(dp, g_ref) < 1e-6
+    w = rng.standard_normal(1000)
+    g = rng.standard_normal(1000)
+    wg, gg = cuda(w), cuda(g)
+    m = torch.zeros_like(wg)
+    v = torch.zeros_like(wg)
+    dl.adam_step(wg, gg, m, v, step=1, lr=1e-2)
+    # first bias-corrected Adam step moves every weight by lr * sign(g) (up to eps)
+    ref = w - 1e-2 * g / (np.abs(g) + 1e-8)
+    assert np.abs(wg.double().cpu().numpy() - ref).max() < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_c2_stack_forward_backward(prec, c2_acq):
+    w = dg.C2
+    V = 256 + 19
+    acq = c2_acq
+    oplan = osh.SHPlan(acq.bvecs, acq.bvals, w.sh_order, w.lb_lambda)
+    plan = dl.SHPlan(acq.bvecs, acq.bvals, w.sh_order, w.lb_lambda)
+    g = dg.lsc_sampled_gradients(w)
+    chans = w.channels
+    olayers, layers = [], []
+    for k in range(len(chans) - 1):
+        op = olsc.LSCPlan(g, 8, 8, w.kernel_sizes, w.angular_distance, w.lb_lambda)
+        p = dl.LSCPlan(g, 8, 8, w.kernel_sizes, w.angular_distance, w.lb_lambda)
+        Wk, bk = dg.lsc_weights(w.config, k, chans[k], chans[k + 1], p.T)
+        Wk = Wk.astype(np.float32).astype(np.float64)
+        bk = bk.astype(np.float32).astype(np.float64)
+        relu = k < len(chans) - 2
+        olayers.append(ostack.Layer(op, Wk, bk, relu))
+        layers.append((p, cuda(Wk), cuda(bk), relu))
+    net = ostack.Stack(oplan, olayers, oplan)
+    batch = dg.stick_ball_batch(acq, V, 3, 20.0, dg.rng_for(w.config, 2, 99))
+    x = batch.x.astype(np.float32).astype(np.float64)
+    tgt = batch.clean.astype(np.float32).astype(np.float64)
+    # GPU forward
+    xg = cuda(x)
+    acts = [dl.signal2sh_fwd(plan, xg, precision=prec)]
+    for p, Wk, bk, relu in layers:
+        acts.append(dl.lsc_fwd(p, acts[-1], Wk, bk, relu=relu, precision=prec))
+    xhat = dl.sh2signal_fwd(plan, acts[-1], precision=prec)
+    loss, dxhat = dl.mse_fwd_bwd(xhat, cuda(tgt))
+    # oracle with the GPU's ReLU pattern (masks from the GPU's activations)
+    xhat_ref, cache = net.forward(x)
+    assert rel(xhat, xhat_ref) <= TOL[prec]
+    gpu_z = [a.double().cpu().numpy() for a in acts[1:]]
+    cache = (cache[0], [gz if L.relu else z for gz, z, L in zip(gpu_z, cache[1], olayers)])
+    l_ref, dxh_ref = ostack.mse(xhat_ref, tgt)
+    assert abs(loss.item() - l_ref) / l_ref <= TOL[prec]
+    dx_ref, dWs_ref, dbs_ref = net.backward(cache, dxhat.double().cpu().numpy())
+    gcur = dl.sh2signal_bwd(plan, dxhat, precision=prec)
+    dWs, dbs = [None] * len(layers), [None] * len(layers)
+    for k in range(len(layers) - 1, -1, -1):
+        p, Wk, bk, relu = layers[k]
+        gcur, dWs[k], dbs[k] = dl.lsc_bwd(p, acts[k], Wk, gcur, a_out=acts[k + 1], relu=relu, precision=prec)
+    dx = dl.signal2sh_bwd(plan, gcur, precision=prec)
+    assert rel(dx, dx_ref) <= TOL[prec]
+    for k in range(len(layers)):
+        assert rel(dWs[k], dWs_ref[k]) <= TOL[prec]
+        assert rel(dbs[k], dbs_ref[k]) <= TOL[prec]
