@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Throughput of the DELIMIT hot path on one MI355X.
+
+One step = forward + backward of the three-shell stack over 1,048,576
+synthetic voxels resident in HBM:
+  Signal2SH (3 shells x 90 directions, SH order 8)
+  -> LSC 3->32 (two rings of 8 points, 30 deg) -> ReLU -> LSC 32->3
+  -> SH2Signal -> q-space MSE against the noise-free signal
+  -> backward through every layer (input, weight and bias gradients).
+
+Prints one JSON line: voxels/s, the roofline position of the dominant
+kernel (per-launch durations from HIP events recorded by the library during
+a second, instrumented pass over the same steps), and the FP64 CPU oracle
+timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--precision fp32|bf16]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxels/s fwd+bwd Signal2SH+LSC+SH2Signal, 3×90 dirs, L=8; % roofline"
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32")
+    ap.add_argument("--voxels", type=int, default=None, help="override the voxel count (default: the workload's)")
+    ap.add_argument("--chunk", type=int, default=1 << 17, help="LSC voxels per workspace pass")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    return ap.parse_args()
+
+
+def make_data(w, V, chunk=1 << 16):
+    import datagen as dg
+
+    acq = dg.make_acquisition(w.config, w.shell_b, w.dirs_per_shell, w.perturb_deg, w.n_b0)
+    n = acq.dw_bvecs.shape[0]
+    x = np.empty((V, n), dtype=np.float32)
+    clean = np.empty((V, n), dtype=np.float32)
+
+    def one(ci):
+        lo = ci * chunk
+        hi = min(V, lo + chunk)
+        b = dg.stick_ball_batch(acq, hi - lo, w.nf_max, w.snr, dg.rng_for(w.config, dg.STREAM_DATA, ci),
+                                dtype=np.float32)
+        x[lo:hi] = b.x
+        clean[lo:hi] = b.clean
+
+    nchunks = (V + chunk - 1) // chunk
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
+        list(ex.map(one, range(nchunks)))
+    return acq, x, clean
+
+
+def roofline(tag, ms, launches, nbytes, flops, prec):
+    t = ms / 1e3
+    hbm_time = nbytes / (HBM_PEAK_GBS * 1e9)
+    mfma_time = flops / (MFMA_PEAK_TFLOPS[prec] * 1e12)
+    if mfma_time > hbm_time:
+        ach = flops / t / 1e12
+        return {"kernel": tag, "bound": "mfma", "achieved": round(ach, 2), "peak": MFMA_PEAK_TFLOPS[prec],
+                "unit": "TFLOP/s", "frac": round(ach / MFMA_PEAK_TFLOPS[prec], 4), "traffic": None,
+                "launches": launches, "avg_launch_ms": round(ms / launches, 4),
+                "alg_flops_per_launch": flops / launches, "alg_bytes_per_launch": nbytes / launches}
+    ach = nbytes / t / 1e9
+    return {"kernel": tag, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "launches": launches,
+            "avg_launch_ms": round(ms / launches, 4), "alg_bytes_per_launch": nbytes / launches,
+            "alg_flops_per_launch": flops / launches}
+
+
+def cpu_baseline(w, acq, target_s):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
+    import datagen as dg
+    from oracle import lsc as olsc
+    from oracle import sh as osh
+    from oracle import stack as ostack
+
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover - threadpoolctl is optional
+        cores = os.cpu_count() or 1
+    plan = osh.SHPlan(acq.bvecs, acq.bvals, w.sh_order, w.lb_lambda)
+    g = dg.lsc_sampled_gradients(w)
+    layers = []
+    ch = w.channels
+    for k in range(len(ch) - 1):
+        p = olsc.LSCPlan(g, w.sh_order_lsc_in, w.sh_order_lsc_out, w.kernel_sizes, w.angular_distance, w.lb_lambda)
+        W, b = dg.lsc_weights(w.config, k, ch[k], ch[k + 1], p.T)
+        layers.append(ostack.Layer(p, W, b, k < len(ch) - 2))
+    net = ostack.Stack(plan, layers, plan)
+    batch = dg.stick_ball_batch(acq, 4096, w.nf_max, w.snr, dg.rng_for(w.config, dg.STREAM_HELDOUT, 0))
+    t0 = time.perf_counter()
+    net.loss_and_grads(batch.x[:128], batch.clean[:128])
+    per_vox = (time.perf_counter() - t0) / 128
+    n = int(min(4096, max(256, target_s / max(per_vox, 1e-9))))
+    n = (n // 256) * 256
+    t0 = time.perf_counter()
+    for lo in range(0, n, 1024):
+        hi = min(n, lo + 1024)
+        net.loss_and_grads(batch.x[lo:hi], batch.clean[lo:hi])
+    dt = time.perf_counter() - t0
+    return {"value": round(n / dt, 2), "unit": "voxels/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{n} voxels of the same workload (stack forward + MSE + backward), NumPy float64, "
+                      f"1024-voxel chunks, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the layers are per-voxel and this build "
+              "measures a single GPU's share; see the sharding notes in the design document.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import datagen as dg
+    import paper_1808_01517_amd as dl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = dg.C2
+    V = args.voxels or w.voxels
+    prec = args.precision
+    t_gen = time.perf_counter()
+    acq, x_h, clean_h = make_data(w, V)
+    t_gen = time.perf_counter() - t_gen
+    print(f"[bench] generated {V} voxels x {x_h.shape[1]} dirs in {t_gen:.1f} s", file=sys.stderr, flush=True)
+
+    plan = dl.SHPlan(acq.bvecs, acq.bvals, w.sh_order, w.lb_lambda)
+    g = dg.lsc_sampled_gradients(w)
+    ch = w.channels
+    layers = []
+    for k in range(len(ch) - 1):
+        p = dl.LSCPlan(g, w.sh_order_lsc_in, w.sh_order_lsc_out, w.kernel_sizes, w.angular_distance, w.lb_lambda)
+        W, b = dg.lsc_weights(w.config, k, ch[k], ch[k + 1], p.T)
+        layers.append((p, torch.from_numpy(W.astype(np.float32)).to(dev), torch.from_numpy(b.astype(np.float32)).to(dev),
+                       k < len(ch) - 2))
+    x = torch.from_numpy(x_h).to(dev)
+    tgt = torch.from_numpy(clean_h).to(dev)
+    del x_h, clean_h
+    S, K = plan.n_shells, plan.K
+    f32 = dict(dtype=torch.float32, device=dev)
+    acts = [torch.empty((V, S, K), **f32)] + [torch.empty((V, ch[k + 1], p.K_out), **f32)
+                                              for k, (p, _, _, _) in enumerate(layers)]
+    grads = [torch.empty_like(a) for a in acts]
+    xhat = torch.empty_like(x)
+    dxhat = torch.empty_like(x)
+    dx = torch.empty_like(x)
+    dWs = [torch.empty_like(Wk) for _, Wk, _, _ in layers]
+    dbs = [torch.empty_like(bk) for _, _, bk, _ in layers]
+    loss = torch.empty((), **f32)
+    mse_ws = torch.empty(dl.lib().dlm_mse_workspace_bytes(x.numel()), dtype=torch.uint8, device=dev)
+    ws_bytes = max(dl.lsc_workspace_bytes(p, ch[k], ch[k + 1], min(V, args.chunk), prec)
+                   for k, (p, _, _, _) in enumerate(layers))
+    ws = dl.Workspace(ws_bytes, dev)
+
+    def step():
+        dl.signal2sh_fwd(plan, x, out=acts[0], precision=prec)
+        for k, (p, Wk, bk, relu) in enumerate(layers):
+            dl.lsc_fwd(p, acts[k], Wk, bk, relu=relu, out=acts[k + 1], precision=prec, workspace=ws)
+        dl.sh2signal_fwd(plan, acts[-1], out=xhat, precision=prec)
+        dl.mse_fwd_bwd(xhat, tgt, outs=(loss, dxhat, mse_ws))
+        dl.sh2signal_bwd(plan, dxhat, out=grads[-1], precision=prec)
+        for k in range(len(layers) - 1, -1, -1):
+            p, Wk, bk, relu = layers[k]
+            dl.lsc_bwd(p, acts[k], Wk, grads[k + 1], a_out=acts[k + 1], relu=relu, precision=prec, workspace=ws,
+                       outs=(grads[k], dWs[k], dbs[k]))
+        dl.signal2sh_bwd(plan, grads[0], out=dx, precision=prec)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(args.steps):
+        step()
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / args.steps
+    value = V * args.steps / (ms_total / 1e3)
+    print(f"[bench] {args.steps} steps: {ms_step:.2f} ms/step (wall {wall / args.steps * 1e3:.2f} ms/step), "
+          f"loss {float(loss):.5f}", file=sys.stderr, flush=True)
+
+    result = {
+        "metric": METRIC, "value": round(value, 1), "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if prec == "fp32" else "bf16", "data": "synthetic",
+        "config": {"workload": w.name, "voxels": V, "shells": len(w.shell_b), "dirs_per_shell": w.dirs_per_shell,
+                   "b0_volumes": w.n_b0, "sh_order": w.sh_order, "lsc_channels": list(ch),
+                   "kernel_sizes": list(w.kernel_sizes), "angular_distance_deg": 30.0, "lsc_form": "resample",
+                   "precision": prec, "lsc_chunk_voxels": min(V, args.chunk)},
+    }
+
+    if not args.no_kernel_timing:
+        dl.timing_reset()
+        dl.timing_enable(True)
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        dl.timing_enable(False)
+        rep = dl.timing_report()
+        kern = {t: {"ms_per_step": round(v[0] / args.steps, 3), "launches_per_step": v[1] // args.steps,
+                    "GB/s": round(v[2] / (v[0] / 1e3) / 1e9, 1) if v[0] > 0 else None,
+                    "TFLOP/s": round(v[3] / (v[0] / 1e3) / 1e12, 2) if v[0] > 0 else None}
+                for t, v in sorted(rep.items(), key=lambda kv: -kv[1][0])}
+        top = max(rep.items(), key=lambda kv: kv[1][0])
+        result["roofline"] = roofline(top[0], *top[1], prec)
+        roof_s = sum(max(v[2] / (HBM_PEAK_GBS * 1e9), v[3] / (MFMA_PEAK_TFLOPS[prec] * 1e12)) for v in rep.values())
+        result["step_roofline_frac"] = round(roof_s / args.steps / (ms_step / 1e3), 4)
+        result["kernels"] = kern
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(w, acq, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -188,6 +188,24 @@ dlm_status dlm_mse_fwd_bwd(const float *pred, const float *target, int64_t n, fl
 dlm_status dlm_adam_step(float *w, const float *g, float *m, float *v, int64_t n, float lr, float beta1,
                          float beta2, float eps, int64_t step, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Measurement support (not part of the layers)
+ * ------------------------------------------------------------------------
+ * While enabled, every kernel the library launches is bracketed by a pair of
+ * HIP events recorded on its launch stream and filed under an operation tag
+ * ("lsc_resample", "signal2sh_fwd", ...) together with the algorithmic bytes
+ * and flops of that launch (input + output bytes and multiply-adds x 2 of the
+ * operation as defined, excluding padding and workspace re-reads).
+ * dlm_timing_count waits for every recorded event and returns the number of
+ * tags; dlm_timing_entry reads tag i (tag copied into a caller buffer of
+ * tag_len bytes).  Event recording adds small gaps between kernels, so time
+ * whole steps with timing disabled. */
+dlm_status dlm_timing_enable(int on);
+dlm_status dlm_timing_reset(void);
+int dlm_timing_count(void);
+dlm_status dlm_timing_entry(int i, char *tag, size_t tag_len, double *total_ms, int64_t *launches,
+                            double *alg_bytes, double *alg_flops);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,7 +21,7 @@ from ._lib import DLM_BF16, DLM_FP32, DelimitError, check, dptr, lib
 __all__ = [
     "SHPlan", "LSCPlan", "precision_code", "signal2sh_fwd", "signal2sh_bwd", "sh2signal_fwd", "sh2signal_bwd",
     "lsc_fwd", "lsc_bwd", "lsc_workspace_bytes", "mse_fwd_bwd", "adam_step", "Workspace", "DelimitError",
-    "sh_basis", "sh_fit_matrix", "lsc_kernel_points",
+    "sh_basis", "sh_fit_matrix", "lsc_kernel_points", "timing_enable", "timing_reset", "timing_report",
 ]
 
 
@@ -264,8 +264,9 @@ def lsc_fwd(plan: LSCPlan, a_in: torch.Tensor, W: torch.Tensor, bias=None, relu:
 
 def lsc_bwd(plan: LSCPlan, a_in: torch.Tensor, W: torch.Tensor, da_out: torch.Tensor, a_out=None, relu=False,
             need_input_grad=True, need_weight_grad=True, need_bias_grad=True, precision="fp32",
-            workspace: Workspace | None = None):
-    """Returns (da_in or None, dW [O][C][T] or None, dbias [O] or None)."""
+            workspace: Workspace | None = None, outs=None):
+    """Returns (da_in or None, dW [O][C][T] or None, dbias [O] or None).
+    `outs` = (da_in, dW, dbias) preallocated float32 tensors (entries may be None)."""
     a_in = _f32_dev(a_in, "a_in")
     W = _f32_dev(W, "W").reshape(W.shape[0], W.shape[1], -1)
     da_out = _f32_dev(da_out, "da_out")
@@ -276,9 +277,12 @@ def lsc_bwd(plan: LSCPlan, a_in: torch.Tensor, W: torch.Tensor, da_out: torch.Te
     prec = precision_code(precision)
     ws = workspace or _default_ws(plan, Cin, O, V, prec, a_in.device)
     dev = a_in.device
-    da_in = torch.empty_like(a_in) if need_input_grad else None
-    dW = torch.empty((O, Cin, plan.T), dtype=torch.float32, device=dev) if (need_weight_grad or need_bias_grad) else None
-    db = torch.empty((O,), dtype=torch.float32, device=dev) if need_bias_grad else None
+    o_da, o_dW, o_db = outs if outs is not None else (None, None, None)
+    da_in = (o_da if o_da is not None else torch.empty_like(a_in)) if need_input_grad else None
+    need_dW = need_weight_grad or need_bias_grad
+    dW = (o_dW if o_dW is not None else torch.empty((O, Cin, plan.T), dtype=torch.float32, device=dev)) \
+        if need_dW else None
+    db = (o_db if o_db is not None else torch.empty((O,), dtype=torch.float32, device=dev)) if need_bias_grad else None
     check(lib().dlm_lsc_bwd(plan.handle, _ptr(a_in), Cin, _ptr(W), O, _ptr(a_out if relu else None), _ptr(da_out),
                             _ptr(da_in), _ptr(dW), _ptr(db), V, int(bool(relu)), ws.ptr(), ws.nbytes, prec,
                             _stream(a_in)))
@@ -286,19 +290,44 @@ def lsc_bwd(plan: LSCPlan, a_in: torch.Tensor, W: torch.Tensor, da_out: torch.Te
 
 
 # --------------------------------------------------------------- training
-def mse_fwd_bwd(pred: torch.Tensor, target: torch.Tensor, need_grad: bool = True):
-    """(loss device scalar, dpred) for loss = mean((pred - target)^2)."""
+def mse_fwd_bwd(pred: torch.Tensor, target: torch.Tensor, need_grad: bool = True, outs=None):
+    """(loss device scalar, dpred) for loss = mean((pred - target)^2).
+    `outs` = (loss, dpred, workspace) preallocated tensors."""
     pred = _f32_dev(pred, "pred")
     target = _f32_dev(target, "target")
     if pred.shape != target.shape:
         raise ValueError("pred and target differ in shape")
     n = pred.numel()
-    ws = torch.empty(lib().dlm_mse_workspace_bytes(n), dtype=torch.uint8, device=pred.device)
-    loss = torch.empty((), dtype=torch.float32, device=pred.device)
-    dpred = torch.empty_like(pred) if need_grad else None
+    if outs is not None:
+        loss, dpred, ws = outs
+    else:
+        ws = torch.empty(lib().dlm_mse_workspace_bytes(n), dtype=torch.uint8, device=pred.device)
+        loss = torch.empty((), dtype=torch.float32, device=pred.device)
+        dpred = torch.empty_like(pred) if need_grad else None
     check(lib().dlm_mse_fwd_bwd(_ptr(pred), _ptr(target), n, _ptr(loss), _ptr(dpred), _ptr(ws), ws.numel(),
                                 _stream(pred)))
     return loss, dpred
+
+
+def timing_enable(on: bool = True) -> None:
+    """Record a HIP event pair around every library launch (measurement only)."""
+    check(lib().dlm_timing_enable(int(bool(on))))
+
+
+def timing_reset() -> None:
+    check(lib().dlm_timing_reset())
+
+
+def timing_report() -> dict:
+    """{tag: (total_ms, launches, algorithmic_bytes, algorithmic_flops)}; waits for recorded events."""
+    n = lib().dlm_timing_count()
+    out = {}
+    for i in range(n):
+        buf = C.create_string_buffer(128)
+        ms, cnt, b, f = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
+        check(lib().dlm_timing_entry(i, buf, 128, C.byref(ms), C.byref(cnt), C.byref(b), C.byref(f)))
+        out[buf.value.decode()] = (ms.value, cnt.value, b.value, f.value)
+    return out
 
 
 def adam_step(w: torch.Tensor, g: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, lr=1e-3, beta1=0.9,

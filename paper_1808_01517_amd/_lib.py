@@ -46,6 +46,11 @@ SIGNATURES = {
     "dlm_mse_workspace_bytes": (C.c_size_t, [_i64]),
     "dlm_mse_fwd_bwd": (_st, [_p, _p, _i64, _p, _p, _p, C.c_size_t, _p]),
     "dlm_adam_step": (_st, [_p, _p, _p, _p, _i64, C.c_float, C.c_float, C.c_float, C.c_float, _i64, _p]),
+    "dlm_timing_enable": (_st, [_int]),
+    "dlm_timing_reset": (_st, []),
+    "dlm_timing_count": (_int, []),
+    "dlm_timing_entry": (_st, [_int, C.c_char_p, C.c_size_t, C.POINTER(_dbl), C.POINTER(_i64), C.POINTER(_dbl),
+                               C.POINTER(_dbl)]),
 }
 
 _lib = None

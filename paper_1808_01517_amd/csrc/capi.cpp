@@ -352,6 +352,8 @@ dlm_status sh_apply(const dlm_sh_plan *p, const float *in, float *out, int64_t V
   // signal side: [V][ndw], coefficient side: [V][S][K]
   const bool to_coef = (op == ShOp::S2shFwd || op == ShOp::Sh2sBwd);
   const DevMat &tab = op == ShOp::S2shFwd ? p->dP : op == ShOp::S2shBwd ? p->dPt : op == ShOp::Sh2sFwd ? p->dB : p->dBt;
+  static const char *const tags[] = {"signal2sh_fwd", "signal2sh_bwd", "sh2signal_fwd", "sh2signal_bwd"};
+  static const KernelOp kops[] = {kOpS2shFwd, kOpS2shBwd, kOpSh2sFwd, kOpSh2sBwd};
   const int shells = p->uniform ? 1 : S;
   for (int s0 = 0; s0 < shells; ++s0) {
     const int64_t N = p->dirs[s0];
@@ -383,6 +385,9 @@ dlm_status sh_apply(const dlm_sh_plan *p, const float *in, float *out, int64_t V
     t.Bf = tab.f32 + tab_off;
     t.Bh = tab.bf16 + tab_off;
     t.b_gs = N * K;
+    t.op = kops[int(op)];
+    const double ng = double(t.groups);
+    TimedScope ts(tags[int(op)], stream, double(V) * ng * (double(N) + K) * 4.0, 2.0 * double(V) * ng * N * K);
     if (launch_table_gemm(t, prec, stream) != 0)
       return fail(DLM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
   }
@@ -586,9 +591,14 @@ dlm_status dlm_lsc_fwd(const dlm_lsc_plan *p, const float *a_in, int C, const fl
   LscWs w = lsc_ws_carve(p, C, O, Vc, ws);
   const int T = p->T, m = int(p->m);
   const int64_t P = p->m * T;
-  if ((s = launched(launch_prepare_weights(W, w.Wt, w.Wh, w.Wth, C, O, T, stream))) != DLM_OK) return s;
+  const double CTO = double(C) * T * O;
+  {
+    TimedScope ts("lsc_prepare_weights", stream, CTO * 12.0, 0.0);
+    if ((s = launched(launch_prepare_weights(W, w.Wt, w.Wh, w.Wth, C, O, T, stream))) != DLM_OK) return s;
+  }
   for (int64_t v0 = 0; v0 < V; v0 += Vc) {
     const int64_t nv = std::min(Vc, V - v0);
+    const double dnv = double(nv);
     TableGemm rs;  // resampling: X[(v,c)][p] = sum_j B_nb[p][j] a[(v,c)][j]
     rs.A = a_in + v0 * C * p->K_in;
     rs.lda = p->K_in;
@@ -599,9 +609,16 @@ dlm_status dlm_lsc_fwd(const dlm_lsc_plan *p, const float *a_in, int C, const fl
     rs.M = nv * C;
     rs.N = int(P);
     rs.K = p->K_in;
-    if ((s = launched(launch_table_gemm(rs, prec, stream))) != DLM_OK) return s;
-    if ((s = launched(launch_lsc_contract_fwd(w.X, W, w.Wh, bias, w.y, nv, C, O, m, T, prec, stream))) != DLM_OK)
-      return s;
+    rs.op = kOpResample;
+    {
+      TimedScope ts("lsc_resample", stream, dnv * C * (p->K_in + double(P)) * 4.0, 2.0 * dnv * C * p->K_in * double(P));
+      if ((s = launched(launch_table_gemm(rs, prec, stream))) != DLM_OK) return s;
+    }
+    {
+      TimedScope ts("lsc_contract_fwd", stream, dnv * (C * double(P) + double(O) * m) * 4.0, 2.0 * dnv * m * CTO);
+      if ((s = launched(launch_lsc_contract_fwd(w.X, W, w.Wh, bias, w.y, nv, C, O, m, T, prec, stream))) != DLM_OK)
+        return s;
+    }
     TableGemm rf;  // refit: a_out[(v,o)][k] = sum_i P_m[k][i] y[(v,o)][i]
     rf.A = w.y;
     rf.lda = m;
@@ -613,6 +630,8 @@ dlm_status dlm_lsc_fwd(const dlm_lsc_plan *p, const float *a_in, int C, const fl
     rf.N = p->K_out;
     rf.K = m;
     rf.relu = fuse_relu ? 1 : 0;
+    rf.op = kOpRefit;
+    TimedScope ts("lsc_refit", stream, dnv * O * (double(m) + p->K_out) * 4.0, 2.0 * dnv * O * m * p->K_out);
     if ((s = launched(launch_table_gemm(rf, prec, stream))) != DLM_OK) return s;
   }
   return ok();
@@ -644,9 +663,14 @@ dlm_status dlm_lsc_bwd(const dlm_lsc_plan *p, const float *a_in, int C, const fl
     return fail(DLM_EWORKSPACE, "workspace of %zu bytes is below the %zu-byte minimum", ws_bytes,
                 lsc_ws_need(p, C, O, std::min<int64_t>(V, kMinChunk)));
   LscWs w = lsc_ws_carve(p, C, O, Vc, ws);
-  if ((s = launched(launch_prepare_weights(W, w.Wt, w.Wh, w.Wth, C, O, T, stream))) != DLM_OK) return s;
+  const double CTO = double(C) * T * O;
+  {
+    TimedScope ts("lsc_prepare_weights", stream, CTO * 12.0, 0.0);
+    if ((s = launched(launch_prepare_weights(W, w.Wt, w.Wh, w.Wth, C, O, T, stream))) != DLM_OK) return s;
+  }
   for (int64_t v0 = 0; v0 < V; v0 += Vc) {
     const int64_t nv = std::min(Vc, V - v0);
+    const double dnv = double(nv);
     TableGemm rb;  // dy[(v,o)][i] = sum_k P_m[k][i] (da * [a_out > 0])[(v,o)][k]
     rb.A = da_out + v0 * O * p->K_out;
     rb.mask = fused_relu ? a_out + v0 * O * p->K_out : nullptr;
@@ -658,7 +682,12 @@ dlm_status dlm_lsc_bwd(const dlm_lsc_plan *p, const float *a_in, int C, const fl
     rb.M = nv * O;
     rb.N = m;
     rb.K = p->K_out;
-    if ((s = launched(launch_table_gemm(rb, prec, stream))) != DLM_OK) return s;
+    rb.op = kOpRefitBwd;
+    {
+      TimedScope ts("lsc_refit_bwd", stream, dnv * O * (p->K_out * (fused_relu ? 2.0 : 1.0) + m) * 4.0,
+                    2.0 * dnv * O * m * p->K_out);
+      if ((s = launched(launch_table_gemm(rb, prec, stream))) != DLM_OK) return s;
+    }
     if (dW) {
       TableGemm rs;  // recompute the neighbourhood matrices X
       rs.A = a_in + v0 * C * p->K_in;
@@ -670,17 +699,31 @@ dlm_status dlm_lsc_bwd(const dlm_lsc_plan *p, const float *a_in, int C, const fl
       rs.M = nv * C;
       rs.N = int(P);
       rs.K = p->K_in;
-      if ((s = launched(launch_table_gemm(rs, prec, stream))) != DLM_OK) return s;
+      rs.op = kOpResample;
+      {
+        TimedScope ts("lsc_resample", stream, dnv * C * (p->K_in + double(P)) * 4.0,
+                      2.0 * dnv * C * p->K_in * double(P));
+        if ((s = launched(launch_table_gemm(rs, prec, stream))) != DLM_OK) return s;
+      }
       const int splits = lsc_weight_splits(nv, m, kWeightSplitTarget);
-      if ((s = launched(launch_lsc_contract_bwd_weight(w.X, w.y, w.part, nv, C, O, m, T, splits, prec, stream))) !=
-          DLM_OK)
-        return s;
+      {
+        TimedScope ts("lsc_bwd_weight", stream, dnv * (C * double(P) + double(O) * m) * 4.0,
+                      2.0 * dnv * m * O * (double(C) * T + 1.0));
+        if ((s = launched(launch_lsc_contract_bwd_weight(w.X, w.y, w.part, nv, C, O, m, T, splits, prec, stream))) !=
+            DLM_OK)
+          return s;
+      }
+      TimedScope ts("lsc_reduce_weight", stream, (double(C) * T + 1.0) * O * 4.0, double(splits) * (C * T + 1.0) * O);
       if ((s = launched(launch_reduce_weight_partials(w.part, splits, dW, dbias, C, O, T, v0 > 0, stream))) != DLM_OK)
         return s;
     }
     if (da_in) {
-      if ((s = launched(launch_lsc_contract_bwd_data(w.y, w.Wt, w.Wth, w.X, nv, C, O, m, T, prec, stream))) != DLM_OK)
-        return s;
+      {
+        TimedScope ts("lsc_bwd_data", stream, dnv * (double(O) * m + C * double(P)) * 4.0, 2.0 * dnv * m * CTO);
+        if ((s = launched(launch_lsc_contract_bwd_data(w.y, w.Wt, w.Wth, w.X, nv, C, O, m, T, prec, stream))) !=
+            DLM_OK)
+          return s;
+      }
       TableGemm ra;  // da[(v,c)][j] = sum_p B_nb[p][j] dX[(v,c)][p]
       ra.A = w.X;
       ra.lda = P;
@@ -691,6 +734,9 @@ dlm_status dlm_lsc_bwd(const dlm_lsc_plan *p, const float *a_in, int C, const fl
       ra.M = nv * C;
       ra.N = p->K_in;
       ra.K = int(P);
+      ra.op = kOpResampleBwd;
+      TimedScope ts("lsc_resample_bwd", stream, dnv * C * (double(P) + p->K_in) * 4.0,
+                    2.0 * dnv * C * double(P) * p->K_in);
       if ((s = launched(launch_table_gemm(ra, prec, stream))) != DLM_OK) return s;
     }
   }
@@ -706,6 +752,7 @@ dlm_status dlm_mse_fwd_bwd(const float *pred, const float *target, int64_t n, fl
   if (!pred || !target || !loss || !ws) return fail(DLM_EINVAL, "null device pointer");
   if (ws_bytes < dlm_mse_workspace_bytes(n)) return fail(DLM_EWORKSPACE, "workspace too small");
   const int nb = mse_blocks(n);
+  TimedScope ts("mse", stream, double(n) * (dpred ? 12.0 : 8.0), 3.0 * double(n));
   dlm_status s = launched(launch_mse(pred, target, n, loss, dpred, static_cast<float *>(ws), nb, stream));
   return s == DLM_OK ? ok() : s;
 }
@@ -719,6 +766,7 @@ dlm_status dlm_adam_step(float *w, const float *g, float *m, float *v, int64_t n
   if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f)) return fail(DLM_EINVAL, "betas must be in [0,1)");
   const float c1 = float(1.0 - std::pow(double(beta1), double(step)));
   const float c2 = float(1.0 - std::pow(double(beta2), double(step)));
+  TimedScope ts("adam", stream, double(n) * 28.0, 10.0 * double(n));
   dlm_status s = launched(launch_adam(w, g, m, v, n, lr, beta1, beta2, eps, c1, c2, stream));
   return s == DLM_OK ? ok() : s;
 }

@@ -35,6 +35,22 @@ struct DevMat {
 };
 
 // ------------------------------------------------------------------ kernels
+// Every operation gets its own kernel symbol (template argument) so that
+// profilers report each one separately.
+enum KernelOp : int {
+  kOpS2shFwd = 0,
+  kOpS2shBwd,
+  kOpSh2sFwd,
+  kOpSh2sBwd,
+  kOpResample,
+  kOpResampleBwd,
+  kOpRefit,
+  kOpRefitBwd,
+  kOpContractFwd,
+  kOpContractBwdData,
+  kOpContractBwdWeight,
+};
+
 // C[r][n] = sum_k A[r][k] * B[n][k] over one group g:
 //   A row r of group g at A + r*lda + g*a_gs, mask (same indexing) optional:
 //     A is replaced by A * (mask > 0);
@@ -52,6 +68,7 @@ struct TableGemm {
   int64_t M = 0;
   int N = 0, K = 0, groups = 1;
   int relu = 0;
+  KernelOp op = kOpS2shFwd;
 };
 int launch_table_gemm(const TableGemm &g, dlm_precision prec, void *stream);
 
@@ -75,5 +92,24 @@ int launch_mse(const float *pred, const float *target, int64_t n, float *loss, f
 int mse_blocks(int64_t n);
 int launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
                 float c1, float c2, void *stream);
+
+// ------------------------------------------------------- timing support
+// When enabled, TimedScope brackets a launch with a HIP event pair on its
+// stream and files it under `tag` with its algorithmic bytes and flops.
+void timing_begin(const char *tag, void *stream);
+void timing_end(void *stream, double alg_bytes, double alg_flops);
+bool timing_on();
+
+struct TimedScope {
+  void *st;
+  double bytes, flops;
+  bool on;
+  TimedScope(const char *tag, void *stream, double b, double f) : st(stream), bytes(b), flops(f), on(timing_on()) {
+    if (on) timing_begin(tag, st);
+  }
+  ~TimedScope() {
+    if (on) timing_end(st, bytes, flops);
+  }
+};
 
 }  // namespace dlm

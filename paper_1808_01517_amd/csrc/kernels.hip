@@ -43,7 +43,7 @@ using CfgNarrow = Cfg<64, 48, 4, 1>;   // N = 45 / 90 style outputs
 using CfgThin = Cfg<128, 16, 4, 1>;    // N <= 16
 
 // ------------------------------------------------------------- FP32 core
-template <class CF, class AL, class BL, class CS>
+template <int OP, class CF, class AL, class BL, class CS>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(AL al, BL bl, CS cs, int64_t M, int N, int K, int ksplit) {
   constexpr int BM = CF::BM, BN = CF::BN, BK = 16;
   constexpr int APT = BM * BK / 256, BPT = BN * BK / 256;
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(AL al, BL bl, CS cs, int6
 }
 
 // ------------------------------------------------------------- BF16 core
-template <class CF, class AL, class BL, class CS>
+template <int OP, class CF, class AL, class BL, class CS>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int64_t M, int N, int K, int ksplit) {
   constexpr int BM = CF::BM, BN = CF::BN, BK = 32, LD = BK + 8;
   constexpr int APT = BM * BK / 256, BPT = BN * BK / 256;
@@ -236,7 +236,7 @@ static Shape pick_shape(int N) {
 
 static int rows_per_block(Shape s) { return s == Shape::Thin ? 128 : 64; }
 
-template <class AL, class BL, class CS>
+template <int OP, class AL, class BL, class CS>
 static int run_gemm(AL al, BL bl, CS cs, int64_t M, int N, int K, int Z, int ksplit, dlm_precision prec,
                     hipStream_t st, Shape shape) {
   if (M <= 0 || N <= 0 || Z <= 0) return 0;
@@ -244,10 +244,10 @@ static int run_gemm(AL al, BL bl, CS cs, int64_t M, int N, int K, int Z, int ksp
   do {                                                                                                    \
     dim3 grid = grid_for<CFG>(M, N, Z);                                                                   \
     if (prec == DLM_BF16)                                                                                 \
-      hipLaunchKernelGGL((gemm_bf16_kernel<CFG, AL, BL, CS>), grid, dim3(256), 0, st, al, bl, cs, M, N, K, \
+      hipLaunchKernelGGL((gemm_bf16_kernel<OP, CFG, AL, BL, CS>), grid, dim3(256), 0, st, al, bl, cs, M, N, K, \
                          ksplit);                                                                         \
     else                                                                                                  \
-      hipLaunchKernelGGL((gemm_f32_kernel<CFG, AL, BL, CS>), grid, dim3(256), 0, st, al, bl, cs, M, N, K,  \
+      hipLaunchKernelGGL((gemm_f32_kernel<OP, CFG, AL, BL, CS>), grid, dim3(256), 0, st, al, bl, cs, M, N, K,  \
                          ksplit);                                                                         \
   } while (0)
   switch (shape) {
@@ -260,7 +260,6 @@ static int run_gemm(AL al, BL bl, CS cs, int64_t M, int N, int K, int Z, int ksp
 }
 
 // ------------------------------------------------------- operand policies
-template <bool MASK>
 struct ARowMajor {
   static constexpr bool kContig = true;
   const float *A, *mask;
@@ -268,7 +267,7 @@ struct ARowMajor {
   __device__ float operator()(int64_t r, int k, int g) const {
     const int64_t o = r * lda + (int64_t)g * gs + k;
     float v = A[o];
-    if constexpr (MASK) v = mask[o] > 0.0f ? v : 0.0f;
+    if (mask) v = mask[o] > 0.0f ? v : 0.0f;
     return v;
   }
 };
@@ -301,18 +300,28 @@ struct CRowMajor {
   }
 };
 
-int launch_table_gemm(const TableGemm &t, dlm_precision prec, void *stream) {
-  hipStream_t st = (hipStream_t)stream;
+template <int OP>
+static int table_gemm_op(const TableGemm &t, dlm_precision prec, hipStream_t st) {
   const Shape sh = pick_shape(t.N);
   CRowMajor cs{t.C, t.ldc, t.c_gs, t.relu};
-  if (prec == DLM_BF16) {
-    BTableH bl{t.Bh, t.b_gs, t.K};
-    if (t.mask) return run_gemm(ARowMajor<true>{t.A, t.mask, t.lda, t.a_gs}, bl, cs, t.M, t.N, t.K, t.groups, 0, prec, st, sh);
-    return run_gemm(ARowMajor<false>{t.A, nullptr, t.lda, t.a_gs}, bl, cs, t.M, t.N, t.K, t.groups, 0, prec, st, sh);
+  ARowMajor al{t.A, t.mask, t.lda, t.a_gs};
+  if (prec == DLM_BF16) return run_gemm<OP>(al, BTableH{t.Bh, t.b_gs, t.K}, cs, t.M, t.N, t.K, t.groups, 0, prec, st, sh);
+  return run_gemm<OP>(al, BTableF{t.Bf, t.b_gs, t.K}, cs, t.M, t.N, t.K, t.groups, 0, prec, st, sh);
+}
+
+int launch_table_gemm(const TableGemm &t, dlm_precision prec, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  switch (t.op) {
+    case kOpS2shFwd: return table_gemm_op<kOpS2shFwd>(t, prec, st);
+    case kOpS2shBwd: return table_gemm_op<kOpS2shBwd>(t, prec, st);
+    case kOpSh2sFwd: return table_gemm_op<kOpSh2sFwd>(t, prec, st);
+    case kOpSh2sBwd: return table_gemm_op<kOpSh2sBwd>(t, prec, st);
+    case kOpResample: return table_gemm_op<kOpResample>(t, prec, st);
+    case kOpResampleBwd: return table_gemm_op<kOpResampleBwd>(t, prec, st);
+    case kOpRefit: return table_gemm_op<kOpRefit>(t, prec, st);
+    case kOpRefitBwd: return table_gemm_op<kOpRefitBwd>(t, prec, st);
+    default: return -3;
   }
-  BTableF bl{t.Bf, t.b_gs, t.K};
-  if (t.mask) return run_gemm(ARowMajor<true>{t.A, t.mask, t.lda, t.a_gs}, bl, cs, t.M, t.N, t.K, t.groups, 0, prec, st, sh);
-  return run_gemm(ARowMajor<false>{t.A, nullptr, t.lda, t.a_gs}, bl, cs, t.M, t.N, t.K, t.groups, 0, prec, st, sh);
 }
 
 // --------------------------------------------- LSC neighbourhood contraction
@@ -366,8 +375,8 @@ int launch_lsc_contract_fwd(const float *X, const float *W, const uint16_t *Wh, 
   ANbhd al{X, m, T, C};
   CSignalY cs{y, bias, m, O};
   const Shape sh = pick_shape(O);
-  if (prec == DLM_BF16) return run_gemm(al, BWeightH{Wh, K}, cs, M, O, K, 1, 0, prec, st, sh);
-  return run_gemm(al, BWeightF{W, K}, cs, M, O, K, 1, 0, prec, st, sh);
+  if (prec == DLM_BF16) return run_gemm<kOpContractFwd>(al, BWeightH{Wh, K}, cs, M, O, K, 1, 0, prec, st, sh);
+  return run_gemm<kOpContractFwd>(al, BWeightF{W, K}, cs, M, O, K, 1, 0, prec, st, sh);
 }
 
 // dy as the A operand: row r = (v, i), column k = o; consecutive rows are
@@ -403,8 +412,8 @@ int launch_lsc_contract_bwd_data(const float *dy, const float *Wt, const uint16_
   ADy al{dy, m, O};
   CNbhd cs{dX, m, T, C};
   const Shape sh = pick_shape(N);
-  if (prec == DLM_BF16) return run_gemm(al, BWeightH{Wth, O}, cs, M, N, O, 1, 0, prec, st, sh);
-  return run_gemm(al, BWeightF{Wt, O}, cs, M, N, O, 1, 0, prec, st, sh);
+  if (prec == DLM_BF16) return run_gemm<kOpContractBwdData>(al, BWeightH{Wth, O}, cs, M, N, O, 1, 0, prec, st, sh);
+  return run_gemm<kOpContractBwdData>(al, BWeightF{Wt, O}, cs, M, N, O, 1, 0, prec, st, sh);
 }
 
 // Weight gradient: rows r = (c, t) plus one bias row (r = C*T, value 1),
@@ -454,7 +463,7 @@ int launch_lsc_contract_bwd_weight(const float *X, const float *dy, float *parti
   // splits beyond `used` would see an empty range; the caller sizes `splits`
   // so that every slice is non-empty and reduces exactly `splits` partials.
   if (used != splits) return -2;
-  return run_gemm(AXt{X, m, T, C}, BDyT{dy, m, O}, CPartial{partial, rows, O}, rows, O, (int)Kfull, splits, ksplit,
+  return run_gemm<kOpContractBwdWeight>(AXt{X, m, T, C}, BDyT{dy, m, O}, CPartial{partial, rows, O}, rows, O, (int)Kfull, splits, ksplit,
                   prec, st, pick_shape(O));
 }
 
