@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32")
+    ap.add_argument("--form", choices=["folded", "resample"], default="folded",
+                    help="LSC evaluation: folded linear map, or the paper's resample/row-dot/refit order")
     ap.add_argument("--voxels", type=int, default=None, help="override the voxel count (default: the workload's)")
     ap.add_argument("--chunk", type=int, default=1 << 17, help="LSC voxels per workspace pass")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
@@ -170,21 +172,22 @@ def main():
     dbs = [torch.empty_like(bk) for _, _, bk, _ in layers]
     loss = torch.empty((), **f32)
     mse_ws = torch.empty(dl.lib().dlm_mse_workspace_bytes(x.numel()), dtype=torch.uint8, device=dev)
-    ws_bytes = max(dl.lsc_workspace_bytes(p, ch[k], ch[k + 1], min(V, args.chunk), prec)
+    form = args.form
+    ws_bytes = max(dl.lsc_workspace_bytes(p, ch[k], ch[k + 1], min(V, args.chunk), prec, form)
                    for k, (p, _, _, _) in enumerate(layers))
     ws = dl.Workspace(ws_bytes, dev)
 
     def step():
         dl.signal2sh_fwd(plan, x, out=acts[0], precision=prec)
         for k, (p, Wk, bk, relu) in enumerate(layers):
-            dl.lsc_fwd(p, acts[k], Wk, bk, relu=relu, out=acts[k + 1], precision=prec, workspace=ws)
+            dl.lsc_fwd(p, acts[k], Wk, bk, relu=relu, out=acts[k + 1], precision=prec, workspace=ws, form=form)
         dl.sh2signal_fwd(plan, acts[-1], out=xhat, precision=prec)
         dl.mse_fwd_bwd(xhat, tgt, outs=(loss, dxhat, mse_ws))
         dl.sh2signal_bwd(plan, dxhat, out=grads[-1], precision=prec)
         for k in range(len(layers) - 1, -1, -1):
             p, Wk, bk, relu = layers[k]
             dl.lsc_bwd(p, acts[k], Wk, grads[k + 1], a_out=acts[k + 1], relu=relu, precision=prec, workspace=ws,
-                       outs=(grads[k], dWs[k], dbs[k]))
+                       outs=(grads[k], dWs[k], dbs[k]), form=form)
         dl.signal2sh_bwd(plan, grads[0], out=dx, precision=prec)
 
     for _ in range(args.warmup):
@@ -212,7 +215,7 @@ def main():
         "vs_baseline": None, "dtype": "f32" if prec == "fp32" else "bf16", "data": "synthetic",
         "config": {"workload": w.name, "voxels": V, "shells": len(w.shell_b), "dirs_per_shell": w.dirs_per_shell,
                    "b0_volumes": w.n_b0, "sh_order": w.sh_order, "lsc_channels": list(ch),
-                   "kernel_sizes": list(w.kernel_sizes), "angular_distance_deg": 30.0, "lsc_form": "resample",
+                   "kernel_sizes": list(w.kernel_sizes), "angular_distance_deg": 30.0, "lsc_form": form,
                    "precision": prec, "lsc_chunk_voxels": min(V, args.chunk)},
     }
 

@@ -125,6 +125,19 @@ dlm_status dlm_sh2signal_bwd(const dlm_sh_plan *plan, const float *dx, float *dc
  * ------------------------------------------------------------------------ */
 typedef struct dlm_lsc_plan dlm_lsc_plan;
 
+/* How an LSC call evaluates the layer.  Both forms compute the same linear
+ * map (up to float rounding order):
+ *  DLM_LSC_RESAMPLE -- the paper's order (Sec. 2.3, Fig. 4): resample the
+ *    neighbourhood matrices X into the workspace, row-dot them with the
+ *    cyclic kernel, refit.  Workspace grows with the voxels per pass.
+ *  DLM_LSC_FOLDED -- by linearity of resample, row dot and refit, the layer
+ *    is a_out[o] = sum_c T_oc a_in[c] + bias[o] P_m 1 with
+ *    T_oc = sum_t W[o][c][t] (P_m B_t), B_t the resampling rows of tap t;
+ *    the small (P_m B_t) tables are built in float64 with the plan, T is
+ *    formed on the device from W on every call, and the layer is one matrix
+ *    product over voxels.  Workspace is independent of V. */
+typedef enum { DLM_LSC_RESAMPLE = 0, DLM_LSC_FOLDED = 1 } dlm_lsc_form;
+
 /* Geometry of one LSC layer: m sampled directions (sampled_gradients host
  * [m][3]), input order sh_order_in, output order sh_order_out, cyclic
  * kernel rings kernel_sizes[n_rings] (points per ring), outer-ring angular
@@ -141,12 +154,13 @@ dlm_status dlm_lsc_plan_info(const dlm_lsc_plan *plan, int *T, int *K_in, int *K
 dlm_status dlm_lsc_plan_tables(const dlm_lsc_plan *plan, double *points, double *B_nb, double *P_m);
 void dlm_lsc_plan_destroy(dlm_lsc_plan *plan);
 
-/* Workspace bytes that dlm_lsc_fwd / dlm_lsc_bwd need to process `V_chunk`
- * voxels per pass for C input and O output channels.  A call given fewer
- * bytes than needed for its V processes the voxels in several passes; the
- * minimum is the size for one 64-voxel pass (less -> DLM_EWORKSPACE). */
+/* Workspace bytes that dlm_lsc_fwd / dlm_lsc_bwd need for C input and O
+ * output channels.  DLM_LSC_RESAMPLE: for `V_chunk` voxels per pass; a call
+ * given fewer bytes than needed for its V processes the voxels in several
+ * passes, the minimum being one 64-voxel pass (less -> DLM_EWORKSPACE).
+ * DLM_LSC_FOLDED: independent of V_chunk. */
 dlm_status dlm_lsc_workspace_bytes(const dlm_lsc_plan *plan, int C, int O, int64_t V_chunk,
-                                   dlm_precision prec, size_t *bytes);
+                                   dlm_lsc_form form, dlm_precision prec, size_t *bytes);
 
 /* LSC forward in the paper's order (Sec. 2.3, Fig. 4):
  *   X[v][c][i*T+t] = sum_j B_nb[i*T+t][j] a_in[v][c][j]   (neighbourhood resampling)
@@ -157,8 +171,8 @@ dlm_status dlm_lsc_workspace_bytes(const dlm_lsc_plan *plan, int C, int O, int64
  * a_in device [V][C][K_in]; W device [O][C][T]; bias device [O] or NULL;
  * a_out device [V][O][K_out]; ws device workspace of ws_bytes. */
 dlm_status dlm_lsc_fwd(const dlm_lsc_plan *plan, const float *a_in, int C, const float *W,
-                       const float *bias, int O, float *a_out, int64_t V, int fuse_relu, void *ws,
-                       size_t ws_bytes, dlm_precision prec, void *stream);
+                       const float *bias, int O, float *a_out, int64_t V, int fuse_relu,
+                       dlm_lsc_form form, void *ws, size_t ws_bytes, dlm_precision prec, void *stream);
 
 /* Adjoint of dlm_lsc_fwd.  da_out device [V][O][K_out] is the gradient of the
  * layer output; if fused_relu != 0 it is masked by a_out > 0 (a_out device
@@ -166,11 +180,13 @@ dlm_status dlm_lsc_fwd(const dlm_lsc_plan *plan, const float *a_in, int C, const
  *   da_in device [V][C][K_in]   = B_nb^T (sum_o W dy),  dy = P_m^T da
  *   dW    device [O][C][T]      = sum_{v,i} dy[v][o][i] X[v][c][i*T+t] (overwritten)
  *   dbias device [O]            = sum_{v,i} dy[v][o][i]                (overwritten)
- * The neighbourhood matrices X are recomputed from a_in, not stored. */
+ * Resample form: the neighbourhood matrices X are recomputed from a_in, not
+ * stored.  Folded form: dW comes from dT_oc = sum_v da_out[v][o] a_in[v][c]^T
+ * contracted with each tap's (P_m B_t). */
 dlm_status dlm_lsc_bwd(const dlm_lsc_plan *plan, const float *a_in, int C, const float *W, int O,
                        const float *a_out, const float *da_out, float *da_in, float *dW, float *dbias,
-                       int64_t V, int fused_relu, void *ws, size_t ws_bytes, dlm_precision prec,
-                       void *stream);
+                       int64_t V, int fused_relu, dlm_lsc_form form, void *ws, size_t ws_bytes,
+                       dlm_precision prec, void *stream);
 
 /* ------------------------------------------------------------------------
  * Training helpers (q-space loss, Sec. 1; optimiser)

@@ -16,13 +16,25 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import DLM_BF16, DLM_FP32, DelimitError, check, dptr, lib
+from ._lib import DLM_BF16, DLM_FP32, DLM_LSC_FOLDED, DLM_LSC_RESAMPLE, DelimitError, check, dptr, lib
 
 __all__ = [
     "SHPlan", "LSCPlan", "precision_code", "signal2sh_fwd", "signal2sh_bwd", "sh2signal_fwd", "sh2signal_bwd",
     "lsc_fwd", "lsc_bwd", "lsc_workspace_bytes", "mse_fwd_bwd", "adam_step", "Workspace", "DelimitError",
     "sh_basis", "sh_fit_matrix", "lsc_kernel_points", "timing_enable", "timing_reset", "timing_report",
+    "form_code", "DEFAULT_FORM",
 ]
+
+
+DEFAULT_FORM = "folded"
+
+
+def form_code(f) -> int:
+    if f in (DLM_LSC_RESAMPLE, "resample"):
+        return DLM_LSC_RESAMPLE
+    if f in (DLM_LSC_FOLDED, "folded", None):
+        return DLM_LSC_FOLDED
+    raise ValueError(f"unknown LSC form {f!r}")
 
 
 def precision_code(p) -> int:
@@ -182,19 +194,19 @@ class Workspace:
         return C.c_void_p(self.buf.data_ptr())
 
 
-def lsc_workspace_bytes(plan: LSCPlan, C_in: int, O: int, V_chunk: int, precision="fp32") -> int:
+def lsc_workspace_bytes(plan: LSCPlan, C_in: int, O: int, V_chunk: int, precision="fp32", form=DEFAULT_FORM) -> int:
     out = C.c_size_t()
-    check(lib().dlm_lsc_workspace_bytes(plan.handle, int(C_in), int(O), int(V_chunk), precision_code(precision),
-                                        C.byref(out)))
+    check(lib().dlm_lsc_workspace_bytes(plan.handle, int(C_in), int(O), int(V_chunk), form_code(form),
+                                        precision_code(precision), C.byref(out)))
     return out.value
 
 
 _ws_cache: dict = {}
 
 
-def _default_ws(plan: LSCPlan, C_in: int, O: int, V: int, prec: int, device) -> Workspace:
-    """A shared workspace sized for up to 65536 voxels per pass."""
-    need = lsc_workspace_bytes(plan, C_in, O, min(max(V, 1), 1 << 16), prec)
+def _default_ws(plan: LSCPlan, C_in: int, O: int, V: int, prec: int, device, form) -> Workspace:
+    """A shared workspace (resample form: up to 65536 voxels per pass)."""
+    need = lsc_workspace_bytes(plan, C_in, O, min(max(V, 1), 1 << 16), prec, form)
     key = str(device)
     ws = _ws_cache.get(key)
     if ws is None or ws.nbytes < need:
@@ -241,7 +253,7 @@ def sh2signal_bwd(plan: SHPlan, dx: torch.Tensor, out=None, precision="fp32") ->
 
 # -------------------------------------------------------------------- LSC
 def lsc_fwd(plan: LSCPlan, a_in: torch.Tensor, W: torch.Tensor, bias=None, relu: bool = False, out=None,
-            precision="fp32", workspace: Workspace | None = None) -> torch.Tensor:
+            precision="fp32", workspace: Workspace | None = None, form=DEFAULT_FORM) -> torch.Tensor:
     """a_in [V][C][K_in], W [O][C][T] (or [O][C][1][T]), bias [O] -> a_out [V][O][K_out]."""
     a_in = _f32_dev(a_in, "a_in")
     W = _f32_dev(W, "W").reshape(W.shape[0], W.shape[1], -1)
@@ -254,17 +266,17 @@ def lsc_fwd(plan: LSCPlan, a_in: torch.Tensor, W: torch.Tensor, bias=None, relu:
         if bias.numel() != O:
             raise ValueError("bias must have O entries")
     prec = precision_code(precision)
-    ws = workspace or _default_ws(plan, Cin, O, V, prec, a_in.device)
+    ws = workspace or _default_ws(plan, Cin, O, V, prec, a_in.device, form)
     if out is None:
         out = torch.empty((V, O, plan.K_out), dtype=torch.float32, device=a_in.device)
     check(lib().dlm_lsc_fwd(plan.handle, _ptr(a_in), Cin, _ptr(W), _ptr(bias), O, _ptr(out), V, int(bool(relu)),
-                            ws.ptr(), ws.nbytes, prec, _stream(a_in)))
+                            form_code(form), ws.ptr(), ws.nbytes, prec, _stream(a_in)))
     return out
 
 
 def lsc_bwd(plan: LSCPlan, a_in: torch.Tensor, W: torch.Tensor, da_out: torch.Tensor, a_out=None, relu=False,
             need_input_grad=True, need_weight_grad=True, need_bias_grad=True, precision="fp32",
-            workspace: Workspace | None = None, outs=None):
+            workspace: Workspace | None = None, outs=None, form=DEFAULT_FORM):
     """Returns (da_in or None, dW [O][C][T] or None, dbias [O] or None).
     `outs` = (da_in, dW, dbias) preallocated float32 tensors (entries may be None)."""
     a_in = _f32_dev(a_in, "a_in")
@@ -275,7 +287,7 @@ def lsc_bwd(plan: LSCPlan, a_in: torch.Tensor, W: torch.Tensor, da_out: torch.Te
     V, Cin, _ = a_in.shape
     O = W.shape[0]
     prec = precision_code(precision)
-    ws = workspace or _default_ws(plan, Cin, O, V, prec, a_in.device)
+    ws = workspace or _default_ws(plan, Cin, O, V, prec, a_in.device, form)
     dev = a_in.device
     o_da, o_dW, o_db = outs if outs is not None else (None, None, None)
     da_in = (o_da if o_da is not None else torch.empty_like(a_in)) if need_input_grad else None
@@ -284,8 +296,8 @@ def lsc_bwd(plan: LSCPlan, a_in: torch.Tensor, W: torch.Tensor, da_out: torch.Te
         if need_dW else None
     db = (o_db if o_db is not None else torch.empty((O,), dtype=torch.float32, device=dev)) if need_bias_grad else None
     check(lib().dlm_lsc_bwd(plan.handle, _ptr(a_in), Cin, _ptr(W), O, _ptr(a_out if relu else None), _ptr(da_out),
-                            _ptr(da_in), _ptr(dW), _ptr(db), V, int(bool(relu)), ws.ptr(), ws.nbytes, prec,
-                            _stream(a_in)))
+                            _ptr(da_in), _ptr(dW), _ptr(db), V, int(bool(relu)), form_code(form), ws.ptr(),
+                            ws.nbytes, prec, _stream(a_in)))
     return da_in, (dW if need_weight_grad else None), db
 
 

@@ -109,7 +109,8 @@ struct dlm_lsc_plan {
   std::vector<int> ks;
   double alpha = 0, lambda = 0;
   std::vector<double> g, points, Bnb, Pm;
-  DevMat dBnb, dBnbT, dPm, dPmT;
+  std::vector<double> Q, pm1;  // Q[t][k][j] = (P_m B_t)[k][j]; pm1 = P_m 1
+  DevMat dBnb, dBnbT, dPm, dPmT, dQ, dpm1;
 };
 
 namespace {
@@ -451,9 +452,26 @@ dlm_status dlm_lsc_plan_create(const double *sampled_gradients, int64_t m, int s
     return fail(DLM_ESINGULAR, "refit: normal matrix of %lld directions at order %d is singular", (long long)m,
                 sh_order_out);
   }
+  // Folded-form tables: Q_t = P_m B_t (B_t = rows i*T+t of B_nb), pm1 = P_m 1.
+  const int Ki = p->K_in, Ko = p->K_out, T = p->T;
+  p->Q.assign(size_t(T) * Ko * Ki, 0.0);
+  for (int t = 0; t < T; ++t)
+    for (int k = 0; k < Ko; ++k) {
+      double *q = p->Q.data() + (size_t(t) * Ko + k) * Ki;
+      for (int64_t i = 0; i < m; ++i) {
+        const double pk = p->Pm[size_t(k) * m + i];
+        const double *b = p->Bnb.data() + (size_t(i) * T + t) * Ki;
+        for (int j = 0; j < Ki; ++j) q[j] += pk * b[j];
+      }
+    }
+  p->pm1.assign(Ko, 0.0);
+  for (int k = 0; k < Ko; ++k)
+    for (int64_t i = 0; i < m; ++i) p->pm1[k] += p->Pm[size_t(k) * m + i];
   std::vector<float> sf;
   std::vector<uint16_t> shh;
-  bool good = upload(p->dBnb, p->Bnb, int(P), p->K_in, nullptr, sf, shh) && hipStreamSynchronize(nullptr) == hipSuccess;
+  bool good = upload(p->dQ, p->Q, T, Ko * Ki, nullptr, sf, shh) && hipStreamSynchronize(nullptr) == hipSuccess;
+  good = good && upload(p->dpm1, p->pm1, 1, Ko, nullptr, sf, shh) && hipStreamSynchronize(nullptr) == hipSuccess;
+  good = good && upload(p->dBnb, p->Bnb, int(P), p->K_in, nullptr, sf, shh) && hipStreamSynchronize(nullptr) == hipSuccess;
   good = good && upload(p->dBnbT, transpose(p->Bnb, int(P), p->K_in), p->K_in, int(P), nullptr, sf, shh) &&
          hipStreamSynchronize(nullptr) == hipSuccess;
   good = good && upload(p->dPm, p->Pm, p->K_out, int(m), nullptr, sf, shh) && hipStreamSynchronize(nullptr) == hipSuccess;
@@ -490,6 +508,8 @@ void dlm_lsc_plan_destroy(dlm_lsc_plan *p) {
   release(p->dBnbT);
   release(p->dPm);
   release(p->dPmT);
+  release(p->dQ);
+  release(p->dpm1);
   delete p;
 }
 
@@ -552,6 +572,39 @@ int64_t lsc_chunk(const dlm_lsc_plan *p, int C, int O, int64_t V, size_t ws_byte
   return a * kMinChunk;
 }
 
+struct FoldWs {
+  float *Tw = nullptr, *TwT = nullptr, *bvec = nullptr, *part = nullptr, *dTw = nullptr;
+  uint16_t *Twh = nullptr, *TwTh = nullptr;
+};
+
+constexpr int kFoldSplitMax = 32;
+
+size_t fold_ws_need(const dlm_lsc_plan *p, int C, int O) {
+  const size_t M = size_t(O) * p->K_out, CK = size_t(C) * p->K_in, N1 = CK + 1;
+  return 2 * align256(M * CK * 4) + 2 * align256(M * CK * 2) + align256(M * 4) +
+         align256(size_t(kFoldSplitMax) * M * N1 * 4) + align256(M * N1 * 4);
+}
+
+FoldWs fold_ws_carve(const dlm_lsc_plan *p, int C, int O, void *ws) {
+  const size_t M = size_t(O) * p->K_out, CK = size_t(C) * p->K_in, N1 = CK + 1;
+  char *b = static_cast<char *>(ws);
+  FoldWs w;
+  w.Tw = reinterpret_cast<float *>(b);
+  b += align256(M * CK * 4);
+  w.TwT = reinterpret_cast<float *>(b);
+  b += align256(M * CK * 4);
+  w.Twh = reinterpret_cast<uint16_t *>(b);
+  b += align256(M * CK * 2);
+  w.TwTh = reinterpret_cast<uint16_t *>(b);
+  b += align256(M * CK * 2);
+  w.bvec = reinterpret_cast<float *>(b);
+  b += align256(M * 4);
+  w.part = reinterpret_cast<float *>(b);
+  b += align256(size_t(kFoldSplitMax) * M * N1 * 4);
+  w.dTw = reinterpret_cast<float *>(b);
+  return w;
+}
+
 dlm_status lsc_check(const dlm_lsc_plan *p, int C, int O, int64_t V, dlm_precision prec) {
   if (!p) return fail(DLM_EINVAL, "plan is NULL");
   if (C < 1 || C > kMaxChannels || O < 1 || O > kMaxChannels)
@@ -568,22 +621,123 @@ dlm_status launched(int rc) {
 
 }  // namespace
 
-dlm_status dlm_lsc_workspace_bytes(const dlm_lsc_plan *p, int C, int O, int64_t V_chunk, dlm_precision prec,
-                                   size_t *bytes) {
+dlm_status dlm_lsc_workspace_bytes(const dlm_lsc_plan *p, int C, int O, int64_t V_chunk, dlm_lsc_form form,
+                                   dlm_precision prec, size_t *bytes) {
   dlm_status s = lsc_check(p, C, O, V_chunk, prec);
   if (s != DLM_OK) return s;
   if (!bytes) return fail(DLM_EINVAL, "bytes is NULL");
-  *bytes = lsc_ws_need(p, C, O, std::max<int64_t>(V_chunk, 1));
+  if (form == DLM_LSC_FOLDED) *bytes = fold_ws_need(p, C, O);
+  else if (form == DLM_LSC_RESAMPLE) *bytes = lsc_ws_need(p, C, O, std::max<int64_t>(V_chunk, 1));
+  else return fail(DLM_EINVAL, "unknown LSC form %d", int(form));
   return ok();
 }
 
+namespace {
+
+dlm_status fold_weights(const dlm_lsc_plan *p, int C, int O, const float *W, const float *bias, const FoldWs &w,
+                        dlm_precision prec, void *stream) {
+  const double KK = double(p->K_out) * p->K_in, M = double(O) * p->K_out, CK = double(C) * p->K_in;
+  {
+    TimedScope ts("lsc_fold", stream, (double(O) * C * p->T + p->T * KK + 2.0 * M * CK) * 4.0,
+                  2.0 * O * C * KK * p->T);
+    if (launch_lsc_fold(W, p->dQ.f32, C, O, p->T, p->K_in, p->K_out, w.Tw, w.TwT, prec == DLM_BF16 ? w.Twh : nullptr,
+                        prec == DLM_BF16 ? w.TwTh : nullptr, stream) != 0)
+      return launched(-1);
+  }
+  return launched(launch_lsc_bias_vec(bias, p->dpm1.f32, O, p->K_out, w.bvec, stream));
+}
+
+dlm_status lsc_fwd_folded(const dlm_lsc_plan *p, const float *a_in, int C, const float *W, const float *bias, int O,
+                          float *a_out, int64_t V, int fuse_relu, void *ws, size_t ws_bytes, dlm_precision prec,
+                          void *stream) {
+  if (ws_bytes < fold_ws_need(p, C, O))
+    return fail(DLM_EWORKSPACE, "workspace of %zu bytes is below the %zu-byte minimum", ws_bytes, fold_ws_need(p, C, O));
+  FoldWs w = fold_ws_carve(p, C, O, ws);
+  dlm_status s = fold_weights(p, C, O, W, bias, w, prec, stream);
+  if (s != DLM_OK) return s;
+  const int M = O * p->K_out, CK = C * p->K_in;
+  TableGemm t;  // a_out[v][(o,k)] = sum_{(c,j)} Tw[(o,k)][(c,j)] a_in[v][(c,j)] + bias[o] (P_m 1)[k]
+  t.A = a_in;
+  t.lda = CK;
+  t.Bf = w.Tw;
+  t.Bh = w.Twh;
+  t.C = a_out;
+  t.ldc = M;
+  t.bias_n = w.bvec;
+  t.M = V;
+  t.N = M;
+  t.K = CK;
+  t.relu = fuse_relu ? 1 : 0;
+  t.op = kOpFoldFwd;
+  TimedScope ts("lsc_folded_fwd", stream, double(V) * (CK + double(M)) * 4.0, 2.0 * double(V) * M * CK);
+  return launched(launch_table_gemm(t, prec, stream));
+}
+
+dlm_status lsc_bwd_folded(const dlm_lsc_plan *p, const float *a_in, int C, const float *W, int O, const float *a_out,
+                          const float *da_out, float *da_in, float *dW, float *dbias, int64_t V, int fused_relu,
+                          void *ws, size_t ws_bytes, dlm_precision prec, void *stream) {
+  if (ws_bytes < fold_ws_need(p, C, O))
+    return fail(DLM_EWORKSPACE, "workspace of %zu bytes is below the %zu-byte minimum", ws_bytes, fold_ws_need(p, C, O));
+  FoldWs w = fold_ws_carve(p, C, O, ws);
+  const int M = O * p->K_out, CK = C * p->K_in, N1 = CK + 1;
+  if (dW && V > int64_t(0x7fffffff)) return fail(DLM_EINVAL, "V = %lld exceeds the 2^31-1 voxels of one call", (long long)V);
+  dlm_status s;
+  const float *mask = fused_relu ? a_out : nullptr;
+  if (da_in && V > 0) {
+    if ((s = fold_weights(p, C, O, W, nullptr, w, prec, stream)) != DLM_OK) return s;
+    TableGemm t;  // da_in[v][(c,j)] = sum_{(o,k)} Tw[(o,k)][(c,j)] (da_out * [a_out > 0])[v][(o,k)]
+    t.A = da_out;
+    t.mask = mask;
+    t.lda = M;
+    t.Bf = w.TwT;
+    t.Bh = w.TwTh;
+    t.C = da_in;
+    t.ldc = CK;
+    t.M = V;
+    t.N = CK;
+    t.K = M;
+    t.op = kOpFoldBwdData;
+    TimedScope ts("lsc_folded_bwd_data", stream, double(V) * (double(M) * (mask ? 2.0 : 1.0) + CK) * 4.0,
+                  2.0 * double(V) * M * CK);
+    if ((s = launched(launch_table_gemm(t, prec, stream))) != DLM_OK) return s;
+  }
+  if (dW) {
+    int splits = 0;
+    if (V > 0) {
+      splits = fold_grad_splits(V, M, N1);
+      if (splits > kFoldSplitMax) return fail(DLM_EINVAL, "internal: too many splits");
+      TimedScope ts("lsc_folded_grad", stream, double(V) * (double(M) * (mask ? 2.0 : 1.0) + CK) * 4.0,
+                    2.0 * double(V) * M * N1);
+      if ((s = launched(launch_lsc_fold_grad(da_out, mask, a_in, V, M, CK, splits, w.part, prec, stream))) != DLM_OK)
+        return s;
+    }
+    {
+      TimedScope ts("lsc_fold_reduce", stream, double(M) * N1 * 4.0, double(splits) * M * N1);
+      if ((s = launched(launch_sum_partials(w.part, splits, int64_t(M) * N1, w.dTw, stream))) != DLM_OK) return s;
+    }
+    TimedScope ts("lsc_unfold", stream, (double(M) * N1 + p->T * double(p->K_out) * p->K_in + double(O) * C * p->T) * 4.0,
+                  2.0 * O * C * p->T * double(p->K_out) * p->K_in);
+    if ((s = launched(launch_lsc_unfold(w.dTw, p->dQ.f32, p->dpm1.f32, C, O, p->T, p->K_in, p->K_out, dW, dbias,
+                                        stream))) != DLM_OK)
+      return s;
+  }
+  return DLM_OK;
+}
+
+}  // namespace
+
 dlm_status dlm_lsc_fwd(const dlm_lsc_plan *p, const float *a_in, int C, const float *W, const float *bias, int O,
-                       float *a_out, int64_t V, int fuse_relu, void *ws, size_t ws_bytes, dlm_precision prec,
-                       void *stream) {
+                       float *a_out, int64_t V, int fuse_relu, dlm_lsc_form form, void *ws, size_t ws_bytes,
+                       dlm_precision prec, void *stream) {
   dlm_status s = lsc_check(p, C, O, V, prec);
   if (s != DLM_OK) return s;
+  if (form != DLM_LSC_RESAMPLE && form != DLM_LSC_FOLDED) return fail(DLM_EINVAL, "unknown LSC form %d", int(form));
   if (V == 0) return ok();
   if (!a_in || !W || !a_out || !ws) return fail(DLM_EINVAL, "null device pointer");
+  if (form == DLM_LSC_FOLDED) {
+    s = lsc_fwd_folded(p, a_in, C, W, bias, O, a_out, V, fuse_relu, ws, ws_bytes, prec, stream);
+    return s == DLM_OK ? ok() : s;
+  }
   const int64_t Vc = lsc_chunk(p, C, O, V, ws_bytes);
   if (Vc == 0)
     return fail(DLM_EWORKSPACE, "workspace of %zu bytes is below the %zu-byte minimum", ws_bytes,
@@ -638,12 +792,20 @@ dlm_status dlm_lsc_fwd(const dlm_lsc_plan *p, const float *a_in, int C, const fl
 }
 
 dlm_status dlm_lsc_bwd(const dlm_lsc_plan *p, const float *a_in, int C, const float *W, int O, const float *a_out,
-                       const float *da_out, float *da_in, float *dW, float *dbias, int64_t V, int fused_relu, void *ws,
-                       size_t ws_bytes, dlm_precision prec, void *stream) {
+                       const float *da_out, float *da_in, float *dW, float *dbias, int64_t V, int fused_relu,
+                       dlm_lsc_form form, void *ws, size_t ws_bytes, dlm_precision prec, void *stream) {
   dlm_status s = lsc_check(p, C, O, V, prec);
   if (s != DLM_OK) return s;
+  if (form != DLM_LSC_RESAMPLE && form != DLM_LSC_FOLDED) return fail(DLM_EINVAL, "unknown LSC form %d", int(form));
   if (!ws) return fail(DLM_EINVAL, "workspace is NULL");
   if (fused_relu && !a_out && V > 0) return fail(DLM_EINVAL, "fused_relu needs the forward output a_out");
+  if (dbias && !dW) return fail(DLM_EINVAL, "dbias without dW is not supported");
+  if (V > 0 && (!a_in || !W || !da_out)) return fail(DLM_EINVAL, "null device pointer");
+  if (form == DLM_LSC_FOLDED) {
+    if (V > 0 && !W) return fail(DLM_EINVAL, "null device pointer");
+    s = lsc_bwd_folded(p, a_in, C, W, O, a_out, da_out, da_in, dW, dbias, V, fused_relu, ws, ws_bytes, prec, stream);
+    return s == DLM_OK ? ok() : s;
+  }
   const int T = p->T, m = int(p->m);
   const int64_t P = p->m * T;
   if (V == 0) {

@@ -49,13 +49,18 @@ enum KernelOp : int {
   kOpContractFwd,
   kOpContractBwdData,
   kOpContractBwdWeight,
+  kOpFoldMake,
+  kOpFoldFwd,
+  kOpFoldBwdData,
+  kOpFoldGrad,
+  kOpFoldUnfold,
 };
 
 // C[r][n] = sum_k A[r][k] * B[n][k] over one group g:
 //   A row r of group g at A + r*lda + g*a_gs, mask (same indexing) optional:
 //     A is replaced by A * (mask > 0);
 //   B (float32 or bf16 table, [N][K] row-major) at B + g*b_gs;
-//   C at C + r*ldc + g*c_gs, optional ReLU.
+//   C at C + r*ldc + g*c_gs, plus bias_n[n] if given, optional ReLU.
 struct TableGemm {
   const float *A = nullptr;
   const float *mask = nullptr;
@@ -64,6 +69,7 @@ struct TableGemm {
   const uint16_t *Bh = nullptr;
   int64_t b_gs = 0;
   float *C = nullptr;
+  const float *bias_n = nullptr;
   int64_t ldc = 0, c_gs = 0;
   int64_t M = 0;
   int N = 0, K = 0, groups = 1;
@@ -92,6 +98,24 @@ int launch_mse(const float *pred, const float *target, int64_t n, float *loss, f
 int mse_blocks(int64_t n);
 int launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
                 float c1, float c2, void *stream);
+
+// ----------------------------------------------------- folded LSC form
+// Tw[(o*Ko+k)][(c*Ki+j)] = sum_t W[o][c][t] Q[t][k][j]  (and the transpose
+// TwT[(c*Ki+j)][(o*Ko+k)]), float32 always, bfloat16 copies when non-null.
+int launch_lsc_fold(const float *W, const float *Q, int C, int O, int T, int Ki, int Ko, float *Tw, float *TwT,
+                    uint16_t *Twh, uint16_t *TwTh, void *stream);
+// bvec[o*Ko+k] = bias[o] * pm1[k]  (zero when bias is null)
+int launch_lsc_bias_vec(const float *bias, const float *pm1, int O, int Ko, float *bvec, void *stream);
+// partial[s][m][n] over voxel slice s: m = (o,k) of g = da_out (masked by
+// a_out > 0 when mask != null), n = (c,j) of a_in plus one ones-column.
+int launch_lsc_fold_grad(const float *da_out, const float *mask, const float *a_in, int64_t V, int M, int CK,
+                         int splits, float *partial, dlm_precision prec, void *stream);
+int fold_grad_splits(int64_t V, int M, int N1);
+// out[i] = sum_s part[s*n + i]
+int launch_sum_partials(const float *part, int splits, int64_t n, float *out, void *stream);
+// dW[(o*C+c)][t] = sum_{k,j} dTw[(o*Ko+k)][c*Ki+j] Q[t][k][j];  db[o] = sum_k dTw[(o*Ko+k)][C*Ki] pm1[k]
+int launch_lsc_unfold(const float *dTw, const float *Q, const float *pm1, int C, int O, int T, int Ki, int Ko,
+                      float *dW, float *db, void *stream);
 
 // ------------------------------------------------------- timing support
 // When enabled, TimedScope brackets a launch with a HIP event pair on its

@@ -17,6 +17,7 @@
 // masked at store.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.h"
@@ -294,7 +295,9 @@ struct CRowMajor {
   float *C;
   int64_t ldc, gs;
   int relu;
+  const float *bias_n;
   __device__ void operator()(int64_t r, int n, int g, float v) const {
+    if (bias_n) v += bias_n[n];
     if (relu) v = fmaxf(v, 0.0f);
     C[r * ldc + (int64_t)g * gs + n] = v;
   }
@@ -303,7 +306,7 @@ struct CRowMajor {
 template <int OP>
 static int table_gemm_op(const TableGemm &t, dlm_precision prec, hipStream_t st) {
   const Shape sh = pick_shape(t.N);
-  CRowMajor cs{t.C, t.ldc, t.c_gs, t.relu};
+  CRowMajor cs{t.C, t.ldc, t.c_gs, t.relu, t.bias_n};
   ARowMajor al{t.A, t.mask, t.lda, t.a_gs};
   if (prec == DLM_BF16) return run_gemm<OP>(al, BTableH{t.Bh, t.b_gs, t.K}, cs, t.M, t.N, t.K, t.groups, 0, prec, st, sh);
   return run_gemm<OP>(al, BTableF{t.Bf, t.b_gs, t.K}, cs, t.M, t.N, t.K, t.groups, 0, prec, st, sh);
@@ -320,6 +323,8 @@ int launch_table_gemm(const TableGemm &t, dlm_precision prec, void *stream) {
     case kOpResampleBwd: return table_gemm_op<kOpResampleBwd>(t, prec, st);
     case kOpRefit: return table_gemm_op<kOpRefit>(t, prec, st);
     case kOpRefitBwd: return table_gemm_op<kOpRefitBwd>(t, prec, st);
+    case kOpFoldFwd: return table_gemm_op<kOpFoldFwd>(t, prec, st);
+    case kOpFoldBwdData: return table_gemm_op<kOpFoldBwdData>(t, prec, st);
     default: return -3;
   }
 }
@@ -478,6 +483,150 @@ int lsc_weight_splits(int64_t V, int m, int target) {
     --s;
   }
   return s < 1 ? 1 : s;
+}
+
+// ------------------------------------------------------- folded LSC form
+// B(n = (k,j), t) = Q[t][k][j]: consecutive n are consecutive in memory.
+struct BQt {
+  static constexpr bool kContig = false;
+  using type = float;
+  const float *Q;
+  int KK;
+  __device__ float operator()(int n, int t, int) const { return Q[(int64_t)t * KK + n]; }
+};
+
+struct CFold {
+  float *Tw, *TwT;
+  uint16_t *Twh, *TwTh;
+  int C, Ki, Ko, O;
+  __device__ void operator()(int64_t r, int n, int, float v) const {
+    const int o = (int)r / C, c = (int)r - o * C;
+    const int k = n / Ki, j = n - k * Ki;
+    const int64_t row = (int64_t)o * Ko + k, col = (int64_t)c * Ki + j;
+    const int64_t a = row * ((int64_t)C * Ki) + col, b = col * ((int64_t)O * Ko) + row;
+    Tw[a] = v;
+    TwT[b] = v;
+    if (Twh) Twh[a] = to_bf16_bits(v);
+    if (TwTh) TwTh[b] = to_bf16_bits(v);
+  }
+};
+
+int launch_lsc_fold(const float *W, const float *Q, int C, int O, int T, int Ki, int Ko, float *Tw, float *TwT,
+                    uint16_t *Twh, uint16_t *TwTh, void *stream) {
+  const int KK = Ko * Ki;
+  return run_gemm<kOpFoldMake>(ARowMajor{W, nullptr, T, 0}, BQt{Q, KK}, CFold{Tw, TwT, Twh, TwTh, C, Ki, Ko, O},
+                               (int64_t)O * C, KK, T, 1, 0, DLM_FP32, (hipStream_t)stream, pick_shape(KK));
+}
+
+__global__ void bias_vec_kernel(const float *bias, const float *pm1, int O, int Ko, float *bvec) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= O * Ko) return;
+  const int o = i / Ko, k = i - o * Ko;
+  bvec[i] = bias ? bias[o] * pm1[k] : 0.0f;
+}
+
+int launch_lsc_bias_vec(const float *bias, const float *pm1, int O, int Ko, float *bvec, void *stream) {
+  hipLaunchKernelGGL(bias_vec_kernel, dim3((O * Ko + 255) / 256), dim3(256), 0, (hipStream_t)stream, bias, pm1, O,
+                     Ko, bvec);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// g^T as the A operand: row m = (o,k), reduction index v; rows are contiguous.
+struct AGradT {
+  static constexpr bool kContig = false;
+  const float *g, *mask;
+  int M;
+  __device__ float operator()(int64_t m, int v, int) const {
+    const int64_t o = (int64_t)v * M + m;
+    float x = g[o];
+    if (mask) x = mask[o] > 0.0f ? x : 0.0f;
+    return x;
+  }
+};
+
+// a^T plus a ones column as the B operand: column n = (c,j) or n = CK (ones).
+struct BActT {
+  static constexpr bool kContig = false;
+  using type = float;
+  const float *a;
+  int CK;
+  __device__ float operator()(int n, int v, int) const { return n < CK ? a[(int64_t)v * CK + n] : 1.0f; }
+};
+
+struct CPartial2 {
+  float *part;
+  int M, N1;
+  __device__ void operator()(int64_t m, int n, int s, float v) const {
+    part[((int64_t)s * M + m) * N1 + n] = v;
+  }
+};
+
+static int split_len(int64_t K, int splits) {
+  const int bk = 32;
+  int ks = (int)((K + splits - 1) / splits);
+  return (ks + bk - 1) / bk * bk;
+}
+
+int fold_grad_splits(int64_t V, int M, int N1) {
+  const int64_t tiles = ((M + 63) / 64) * ((N1 + 63) / 64);
+  int s = (int)std::min<int64_t>(32, std::max<int64_t>(1, (2048 + tiles - 1) / tiles));
+  s = (int)std::min<int64_t>(s, std::max<int64_t>(1, V / 256));
+  while (s > 1 && (V + split_len(V, s) - 1) / split_len(V, s) != s) --s;
+  return s;
+}
+
+int launch_lsc_fold_grad(const float *da_out, const float *mask, const float *a_in, int64_t V, int M, int CK,
+                         int splits, float *partial, dlm_precision prec, void *stream) {
+  const int N1 = CK + 1;
+  const int ks = split_len(V, splits);
+  if ((V + ks - 1) / ks != splits) return -2;
+  return run_gemm<kOpFoldGrad>(AGradT{da_out, mask, M}, BActT{a_in, CK}, CPartial2{partial, M, N1}, M, N1, (int)V,
+                               splits, ks, prec, (hipStream_t)stream, pick_shape(N1));
+}
+
+__global__ void sum_partials_kernel(const float *part, int splits, int64_t n, float *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.0f;
+  for (int p = 0; p < splits; ++p) s += part[(int64_t)p * n + i];
+  out[i] = s;
+}
+
+int launch_sum_partials(const float *part, int splits, int64_t n, float *out, void *stream) {
+  hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, part,
+                     splits, n, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// dTw viewed per (o,c): row r = (o,c), column k = (kk,j) of the Ko x Ki block.
+struct AUnfold {
+  static constexpr bool kContig = true;
+  const float *dTw;
+  int C, Ki, Ko, N1;
+  __device__ float operator()(int64_t r, int k, int) const {
+    const int o = (int)r / C, c = (int)r - o * C;
+    const int kk = k / Ki, j = k - kk * Ki;
+    return dTw[((int64_t)o * Ko + kk) * N1 + (int64_t)c * Ki + j];
+  }
+};
+
+__global__ void bias_grad_kernel(const float *dTw, const float *pm1, int O, int Ko, int N1, int CK, float *db) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= O) return;
+  float s = 0.0f;
+  for (int k = 0; k < Ko; ++k) s += dTw[((int64_t)o * Ko + k) * N1 + CK] * pm1[k];
+  db[o] = s;
+}
+
+int launch_lsc_unfold(const float *dTw, const float *Q, const float *pm1, int C, int O, int T, int Ki, int Ko,
+                      float *dW, float *db, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int N1 = C * Ki + 1;
+  int rc = run_gemm<kOpFoldUnfold>(AUnfold{dTw, C, Ki, Ko, N1}, BTableF{Q, 0, Ko * Ki}, CRowMajor{dW, T, 0, 0, nullptr},
+                                   (int64_t)O * C, T, Ko * Ki, 1, 0, DLM_FP32, st, pick_shape(T));
+  if (rc != 0 || !db) return rc;
+  hipLaunchKernelGGL(bias_grad_kernel, dim3((O + 63) / 64), dim3(64), 0, st, dTw, pm1, O, Ko, N1, C * Ki, db);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 // --------------------------------------------------------- small kernels

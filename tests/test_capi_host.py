@@ -83,6 +83,6 @@ def test_status_codes(L):
     assert lib.dlm_status_str(L.DLM_EWORKSPACE) == b"workspace too small"
     # compute calls validate before touching the device
     assert lib.dlm_signal2sh_fwd(None, None, None, 10, 0, None) == L.DLM_EINVAL
-    assert lib.dlm_lsc_fwd(None, None, 3, None, None, 3, None, 10, 0, None, 0, 0, None) == L.DLM_EINVAL
+    assert lib.dlm_lsc_fwd(None, None, 3, None, None, 3, None, 10, 0, 0, None, 0, 0, None) == L.DLM_EINVAL
     assert lib.dlm_mse_fwd_bwd(None, None, 0, None, None, None, 0, None) == L.DLM_EINVAL
     assert lib.dlm_adam_step(None, None, None, None, 5, 1e-3, 0.9, 0.999, 1e-8, 0, None) == L.DLM_EINVAL

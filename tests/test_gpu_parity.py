@@ -75,6 +75,7 @@ def _lsc_case(C, O, L_in, L_out, ks, m_dirs, V, seed):
     return oplan, plan, W.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64), a
 
 
+@pytest.mark.parametrize("form", ["resample", "folded"])
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("case", [
     (1, 8, 4, 4, (6, 6), 30, 517),
@@ -83,18 +84,18 @@ def _lsc_case(C, O, L_in, L_out, ks, m_dirs, V, seed):
     (3, 5, 4, 8, (8, 8), 90, 131),
 ])
 @pytest.mark.parametrize("relu", [False, True])
-def test_lsc_forward_backward(prec, case, relu):
+def test_lsc_forward_backward(prec, case, relu, form):
     C, O, L_in, L_out, ks, m, V = case
     oplan, plan, W, b, a = _lsc_case(C, O, L_in, L_out, ks, m, V, 5)
     out_ref, z = olsc.lsc_forward(oplan, a, W, b, relu)
     ag, Wg, bg = cuda(a), cuda(W), cuda(b)
-    out = dl.lsc_fwd(plan, ag, Wg, bg, relu=relu, precision=prec)
+    out = dl.lsc_fwd(plan, ag, Wg, bg, relu=relu, precision=prec, form=form)
     assert rel(out, out_ref) <= TOL[prec]
     da_out = np.random.default_rng(9).standard_normal(out_ref.shape).astype(np.float32).astype(np.float64)
     # mask from the GPU's own forward output so both sides use the same ReLU pattern
     z_mask = out.double().cpu().numpy() if relu else z
     da_ref, dW_ref, db_ref = olsc.lsc_backward(oplan, a, W, z_mask, da_out, relu)
-    da, dW, db = dl.lsc_bwd(plan, ag, Wg, cuda(da_out), a_out=out, relu=relu, precision=prec)
+    da, dW, db = dl.lsc_bwd(plan, ag, Wg, cuda(da_out), a_out=out, relu=relu, precision=prec, form=form)
     assert rel(da, da_ref) <= TOL[prec]
     assert rel(dW, dW_ref) <= TOL[prec]
     assert rel(db, db_ref) <= TOL[prec]
@@ -105,27 +106,28 @@ def test_lsc_chunked_workspace_matches_single_pass():
     C, O = 3, 32
     oplan, plan, W, b, a = _lsc_case(C, O, 8, 8, (8, 8), 90, 333, 7)
     ag, Wg, bg = cuda(a), cuda(W), cuda(b)
-    small = dl.Workspace(dl.lsc_workspace_bytes(plan, C, O, 64), DEV)
-    big = dl.Workspace(dl.lsc_workspace_bytes(plan, C, O, 333), DEV)
-    o1 = dl.lsc_fwd(plan, ag, Wg, bg, relu=True, workspace=small)
-    o2 = dl.lsc_fwd(plan, ag, Wg, bg, relu=True, workspace=big)
+    small = dl.Workspace(dl.lsc_workspace_bytes(plan, C, O, 64, form="resample"), DEV)
+    big = dl.Workspace(dl.lsc_workspace_bytes(plan, C, O, 333, form="resample"), DEV)
+    o1 = dl.lsc_fwd(plan, ag, Wg, bg, relu=True, workspace=small, form="resample")
+    o2 = dl.lsc_fwd(plan, ag, Wg, bg, relu=True, workspace=big, form="resample")
     assert torch.equal(o1, o2)
     g = cuda(np.random.default_rng(1).standard_normal(o1.shape))
-    r1 = dl.lsc_bwd(plan, ag, Wg, g, a_out=o1, relu=True, workspace=small)
-    r2 = dl.lsc_bwd(plan, ag, Wg, g, a_out=o2, relu=True, workspace=big)
+    r1 = dl.lsc_bwd(plan, ag, Wg, g, a_out=o1, relu=True, workspace=small, form="resample")
+    r2 = dl.lsc_bwd(plan, ag, Wg, g, a_out=o2, relu=True, workspace=big, form="resample")
     assert torch.equal(r1[0], r2[0])
     assert rel(r1[1], r2[1].double().cpu().numpy()) < 1e-6
     ref = olsc.lsc_backward(oplan, a, W, o1.double().cpu().numpy(), g.double().cpu().numpy(), True)
     assert rel(r1[1], ref[1]) <= 1e-5 and rel(r1[2], ref[2]) <= 1e-5
 
 
-def test_lsc_deterministic():
+@pytest.mark.parametrize("form", ["resample", "folded"])
+def test_lsc_deterministic(form):
     C, O = 32, 3
     _, plan, W, b, a = _lsc_case(C, O, 8, 8, (8, 8), 90, 257, 8)
     ag, Wg = cuda(a), cuda(W)
     g = cuda(np.random.default_rng(2).standard_normal((257, O, 45)))
-    r1 = dl.lsc_bwd(plan, ag, Wg, g)
-    r2 = dl.lsc_bwd(plan, ag, Wg, g)
+    r1 = dl.lsc_bwd(plan, ag, Wg, g, form=form)
+    r2 = dl.lsc_bwd(plan, ag, Wg, g, form=form)
     for x, y in zip(r1, r2):
         assert torch.equal(x, y)
 
@@ -149,8 +151,9 @@ def test_mse_and_adam():
     assert np.abs(wg.double().cpu().numpy() - ref).max() < 1e-6
 
 
+@pytest.mark.parametrize("form", ["resample", "folded"])
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_c2_stack_forward_backward(prec, c2_acq):
+def test_c2_stack_forward_backward(prec, form, c2_acq):
     w = dg.C2
     V = 256 + 19
     acq = c2_acq
@@ -176,7 +179,7 @@ def test_c2_stack_forward_backward(prec, c2_acq):
     xg = cuda(x)
     acts = [dl.signal2sh_fwd(plan, xg, precision=prec)]
     for p, Wk, bk, relu in layers:
-        acts.append(dl.lsc_fwd(p, acts[-1], Wk, bk, relu=relu, precision=prec))
+        acts.append(dl.lsc_fwd(p, acts[-1], Wk, bk, relu=relu, precision=prec, form=form))
     xhat = dl.sh2signal_fwd(plan, acts[-1], precision=prec)
     loss, dxhat = dl.mse_fwd_bwd(xhat, cuda(tgt))
     # oracle with the GPU's ReLU pattern (masks from the GPU's activations)
@@ -191,9 +194,35 @@ def test_c2_stack_forward_backward(prec, c2_acq):
     dWs, dbs = [None] * len(layers), [None] * len(layers)
     for k in range(len(layers) - 1, -1, -1):
         p, Wk, bk, relu = layers[k]
-        gcur, dWs[k], dbs[k] = dl.lsc_bwd(p, acts[k], Wk, gcur, a_out=acts[k + 1], relu=relu, precision=prec)
+        gcur, dWs[k], dbs[k] = dl.lsc_bwd(p, acts[k], Wk, gcur, a_out=acts[k + 1], relu=relu, precision=prec,
+                                          form=form)
     dx = dl.signal2sh_bwd(plan, gcur, precision=prec)
     assert rel(dx, dx_ref) <= TOL[prec]
     for k in range(len(layers)):
         assert rel(dWs[k], dWs_ref[k]) <= TOL[prec]
         assert rel(dbs[k], dbs_ref[k]) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_folded_matches_resample_form(prec):
+    # both forms evaluate the same linear map; they agree to rounding
+    C, O = 3, 32
+    _, plan, W, b, a = _lsc_case(C, O, 8, 8, (8, 8), 90, 700, 12)
+    ag, Wg, bg = cuda(a), cuda(W), cuda(b)
+    o1 = dl.lsc_fwd(plan, ag, Wg, bg, relu=True, precision=prec, form="resample")
+    o2 = dl.lsc_fwd(plan, ag, Wg, bg, relu=True, precision=prec, form="folded")
+    assert rel(o2, o1.double().cpu().numpy()) <= TOL[prec]
+
+
+def test_lsc_empty_batch_zeroes_weight_grads():
+    C, O = 3, 4
+    _, plan, W, b, a = _lsc_case(C, O, 4, 4, (6, 6), 30, 1, 13)
+    Wg = cuda(W)
+    for form in ("resample", "folded"):
+        dW = torch.full((O, C, plan.T), 7.0, device=DEV)
+        db = torch.full((O,), 7.0, device=DEV)
+        empty = torch.empty((0, C, plan.K_in), device=DEV)
+        dl.lsc_bwd(plan, empty, Wg, torch.empty((0, O, plan.K_out), device=DEV), need_input_grad=False,
+                   outs=(None, dW, db), form=form)
+        torch.cuda.synchronize()
+        assert float(dW.abs().max()) == 0.0 and float(db.abs().max()) == 0.0
