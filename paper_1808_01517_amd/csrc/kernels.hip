@@ -39,21 +39,48 @@ struct Cfg {
   static_assert(WM * WN == 4, "four waves per block");
   static_assert(TM * WM * 16 == BM && TN * WN * 16 == BN, "tile shape");
 };
-using CfgSquare = Cfg<64, 64, 2, 2>;   // general
-using CfgNarrow = Cfg<64, 48, 4, 1>;   // N = 45 / 90 style outputs
-using CfgThin = Cfg<128, 16, 4, 1>;    // N <= 16
+using Cfg96 = Cfg<128, 96, 2, 2>;    // N = 1440, 2880 (15/30 tiles exactly)
+using Cfg144 = Cfg<128, 144, 4, 1>;  // 96 < N <= 144 (N = 135)
+using Cfg48 = Cfg<64, 48, 4, 1>;     // N <= 96 (N = 45, 90)
+using Cfg16 = Cfg<128, 16, 4, 1>;    // N <= 16
+using Cfg64 = Cfg<64, 64, 2, 2>;     // everything else
+
+// Row stride (in 32-bit words) of a k-major LDS tile whose rows hold B
+// entries: padded so that the four k-rows one MFMA operand read touches
+// start 16 banks apart (conflict-free for 32 and 64 banks).
+constexpr int lds_stride(int B) {
+  return (B % 64 == 16 || B % 64 == 48) ? B : B + ((B % 64) < 16 ? 16 - B % 64 : (B % 64) < 48 ? 48 - B % 64 : 80 - B % 64);
+}
+
+// Block index -> (M tile, N tile).  Workgroups are dispatched round-robin
+// over the 8 XCDs; consecutive logical tiles are gathered onto one XCD so
+// the N tiles that share an A row-block run together and hit the same L2.
+struct TileMap {
+  int mt, nt;
+  __device__ TileMap(int b, int nbM, int nbN) {
+    const int total = nbM * nbN;
+    const int q = total >> 3, r = total & 7;
+    const int xcd = b & 7, local = b >> 3;
+    const int L = xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+    mt = L / nbN;
+    nt = L - mt * nbN;
+  }
+};
 
 // ------------------------------------------------------------- FP32 core
 template <int OP, class CF, class AL, class BL, class CS>
-__global__ __launch_bounds__(256) void gemm_f32_kernel(AL al, BL bl, CS cs, int64_t M, int N, int K, int ksplit) {
+__global__ __launch_bounds__(256) void gemm_f32_kernel(AL al, BL bl, CS cs, int64_t M, int N, int K, int ksplit,
+                                                       int nbM, int nbN) {
   constexpr int BM = CF::BM, BN = CF::BN, BK = 16;
-  constexpr int APT = BM * BK / 256, BPT = BN * BK / 256;
-  __shared__ float As[BK][BM + 4];
-  __shared__ float Bs[BK][BN + 4];
+  constexpr int SA = lds_stride(BM), SB = lds_stride(BN);
+  constexpr int APT = BM * BK / 256, BPT = (BN * BK + 255) / 256;
+  __shared__ float As[2][BK * SA];
+  __shared__ float Bs[2][BK * SB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % CF::WM, wn = wave / CF::WM;
-  const int64_t m0 = (int64_t)blockIdx.x * BM;
-  const int n0 = blockIdx.y * BN;
+  const TileMap tm(blockIdx.x, nbM, nbN);
+  const int64_t m0 = (int64_t)tm.mt * BM;
+  const int n0 = tm.nt * BN;
   const int g = blockIdx.z;
   int kbeg = 0, kend = K;
   if (ksplit > 0) {
@@ -78,7 +105,23 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(AL al, BL bl, CS cs, int6
       if constexpr (BL::kContig) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
       const int n = n0 + nn;
       const int k = k0 + kk;
-      rb[p] = (n < N && k < kend) ? bl(n, k, g) : 0.0f;
+      rb[p] = (e < BN * BK && n < N && k < kend) ? bl(n, k, g) : 0.0f;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < APT; ++p) {
+      const int e = tid + p * 256;
+      int mm, kk;
+      if constexpr (AL::kContig) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
+      As[buf][kk * SA + mm] = ra[p];
+    }
+#pragma unroll
+    for (int p = 0; p < BPT; ++p) {
+      const int e = tid + p * 256;
+      int nn, kk;
+      if constexpr (BL::kContig) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
+      if (e < BN * BK) Bs[buf][kk * SB + nn] = rb[p];
     }
   };
   floatx4 acc[CF::TM][CF::TN];
@@ -87,36 +130,31 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(AL al, BL bl, CS cs, int6
 #pragma unroll
     for (int j = 0; j < CF::TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  load(kbeg);
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-#pragma unroll
-    for (int p = 0; p < APT; ++p) {
-      const int e = tid + p * 256;
-      int mm, kk;
-      if constexpr (AL::kContig) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
-      As[kk][mm] = ra[p];
-    }
-#pragma unroll
-    for (int p = 0; p < BPT; ++p) {
-      const int e = tid + p * 256;
-      int nn, kk;
-      if constexpr (BL::kContig) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
-      Bs[kk][nn] = rb[p];
-    }
+  const int niter = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  if (niter > 0) {
+    load(kbeg);
+    stash(0);
     __syncthreads();
-    if (k0 + BK < kend) load(k0 + BK);
+  }
+  for (int it = 0; it < niter; ++it) {
+    const int cur = it & 1;
+    if (it + 1 < niter) load(kbeg + (it + 1) * BK);
+    const float *Ac = As[cur];
+    const float *Bc = Bs[cur];
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       float a[CF::TM], b[CF::TN];
+      const int row = kk + (lane >> 4);
 #pragma unroll
-      for (int i = 0; i < CF::TM; ++i) a[i] = As[kk + (lane >> 4)][(wm * CF::TM + i) * 16 + (lane & 15)];
+      for (int i = 0; i < CF::TM; ++i) a[i] = Ac[row * SA + (wm * CF::TM + i) * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < CF::TN; ++j) b[j] = Bs[kk + (lane >> 4)][(wn * CF::TN + j) * 16 + (lane & 15)];
+      for (int j = 0; j < CF::TN; ++j) b[j] = Bc[row * SB + (wn * CF::TN + j) * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < CF::TM; ++i)
 #pragma unroll
         for (int j = 0; j < CF::TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    if (it + 1 < niter) stash(cur ^ 1);
     __syncthreads();
   }
 #pragma unroll
@@ -132,44 +170,87 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(AL al, BL bl, CS cs, int6
 }
 
 // ------------------------------------------------------------- BF16 core
+// LDS holds m-major rows of BK bfloat16 (k contiguous) so that each lane
+// reads its 8 consecutive k as one 16-byte load.
 template <int OP, class CF, class AL, class BL, class CS>
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int64_t M, int N, int K, int ksplit) {
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int64_t M, int N, int K, int ksplit,
+                                                        int nbM, int nbN) {
   constexpr int BM = CF::BM, BN = CF::BN, BK = 32, LD = BK + 8;
-  constexpr int APT = BM * BK / 256, BPT = BN * BK / 256;
-  __shared__ __attribute__((aligned(16))) uint16_t As[BM * LD];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LD];
+  constexpr int APT = BM * BK / 256, BPT = (BN * BK + 255) / 256;
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % CF::WM, wn = wave / CF::WM;
-  const int64_t m0 = (int64_t)blockIdx.x * BM;
-  const int n0 = blockIdx.y * BN;
+  const TileMap tm(blockIdx.x, nbM, nbN);
+  const int64_t m0 = (int64_t)tm.mt * BM;
+  const int n0 = tm.nt * BN;
   const int g = blockIdx.z;
   int kbeg = 0, kend = K;
   if (ksplit > 0) {
     kbeg = g * ksplit;
     kend = min(K, kbeg + ksplit);
   }
-  uint16_t ra[APT], rb[BPT];
+  // K-contiguous operands: each thread converts pairs of consecutive k and
+  // stores them as one 32-bit word.
+  uint32_t ra[APT], rb[BPT];
+  // Every thread converts pairs of consecutive k and stores them as one
+  // 32-bit LDS word; for m/n-contiguous operands the pair's two loads are
+  // each coalesced across the consecutive m (n) of neighbouring threads.
+  auto ida = [&](int e, int &mm, int &kk) {
+    if constexpr (AL::kContig) { kk = 2 * (e % (BK / 2)); mm = e / (BK / 2); } else { mm = e % BM; kk = 2 * (e / BM); }
+  };
+  auto idb = [&](int e, int &nn, int &kk) {
+    if constexpr (BL::kContig) { kk = 2 * (e % (BK / 2)); nn = e / (BK / 2); } else { nn = e % BN; kk = 2 * (e / BN); }
+  };
+  constexpr int AITEMS = APT / 2;
+  constexpr int BITEMS = (BPT + 1) / 2;
+  constexpr int BTOTAL = BN * BK / 2;
+  auto cvt = [&](float f) -> uint32_t { return (uint32_t)to_bf16_bits(f); };
   auto load = [&](int k0) {
 #pragma unroll
-    for (int p = 0; p < APT; ++p) {
+    for (int p = 0; p < AITEMS; ++p) {
       const int e = tid + p * 256;
       int mm, kk;
-      if constexpr (AL::kContig) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
+      ida(e, mm, kk);
       const int64_t r = m0 + mm;
       const int k = k0 + kk;
-      ra[p] = (r < M && k < kend) ? to_bf16_bits(al(r, k, g)) : uint16_t(0);
+      const uint32_t lo = (r < M && k < kend) ? cvt(al(r, k, g)) : 0u;
+      const uint32_t hi = (r < M && k + 1 < kend) ? cvt(al(r, k + 1, g)) : 0u;
+      ra[p] = lo | (hi << 16);
     }
 #pragma unroll
-    for (int p = 0; p < BPT; ++p) {
+    for (int p = 0; p < BITEMS; ++p) {
       const int e = tid + p * 256;
       int nn, kk;
-      if constexpr (BL::kContig) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
+      idb(e, nn, kk);
       const int n = n0 + nn;
       const int k = k0 + kk;
-      if constexpr (std::is_same<typename BL::type, float>::value)
-        rb[p] = (n < N && k < kend) ? to_bf16_bits(bl(n, k, g)) : uint16_t(0);
-      else
-        rb[p] = (n < N && k < kend) ? bl(n, k, g) : uint16_t(0);
+      const bool okn = e < BTOTAL && n < N;
+      uint32_t lo = 0u, hi = 0u;
+      if constexpr (std::is_same<typename BL::type, float>::value) {
+        lo = (okn && k < kend) ? cvt(bl(n, k, g)) : 0u;
+        hi = (okn && k + 1 < kend) ? cvt(bl(n, k + 1, g)) : 0u;
+      } else {
+        lo = (okn && k < kend) ? (uint32_t)bl(n, k, g) : 0u;
+        hi = (okn && k + 1 < kend) ? (uint32_t)bl(n, k + 1, g) : 0u;
+      }
+      rb[p] = lo | (hi << 16);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < AITEMS; ++p) {
+      const int e = tid + p * 256;
+      int mm, kk;
+      ida(e, mm, kk);
+      *reinterpret_cast<uint32_t *>(&As[buf][mm * LD + kk]) = ra[p];
+    }
+#pragma unroll
+    for (int p = 0; p < BITEMS; ++p) {
+      const int e = tid + p * 256;
+      int nn, kk;
+      idb(e, nn, kk);
+      if (e < BTOTAL) *reinterpret_cast<uint32_t *>(&Bs[buf][nn * LD + kk]) = rb[p];
     }
   };
   floatx4 acc[CF::TM][CF::TN];
@@ -178,35 +259,27 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
 #pragma unroll
     for (int j = 0; j < CF::TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  load(kbeg);
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-#pragma unroll
-    for (int p = 0; p < APT; ++p) {
-      const int e = tid + p * 256;
-      int mm, kk;
-      if constexpr (AL::kContig) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
-      As[mm * LD + kk] = ra[p];
-    }
-#pragma unroll
-    for (int p = 0; p < BPT; ++p) {
-      const int e = tid + p * 256;
-      int nn, kk;
-      if constexpr (BL::kContig) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
-      Bs[nn * LD + kk] = rb[p];
-    }
+  const int niter = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  if (niter > 0) {
+    load(kbeg);
+    stash(0);
     __syncthreads();
-    if (k0 + BK < kend) load(k0 + BK);
+  }
+  for (int it = 0; it < niter; ++it) {
+    const int cur = it & 1;
+    if (it + 1 < niter) load(kbeg + (it + 1) * BK);
     bf16x8 a[CF::TM], b[CF::TN];
 #pragma unroll
     for (int i = 0; i < CF::TM; ++i)
-      a[i] = *reinterpret_cast<const bf16x8 *>(&As[((wm * CF::TM + i) * 16 + (lane & 15)) * LD + 8 * (lane >> 4)]);
+      a[i] = *reinterpret_cast<const bf16x8 *>(&As[cur][((wm * CF::TM + i) * 16 + (lane & 15)) * LD + 8 * (lane >> 4)]);
 #pragma unroll
     for (int j = 0; j < CF::TN; ++j)
-      b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[((wn * CF::TN + j) * 16 + (lane & 15)) * LD + 8 * (lane >> 4)]);
+      b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[cur][((wn * CF::TN + j) * 16 + (lane & 15)) * LD + 8 * (lane >> 4)]);
 #pragma unroll
     for (int i = 0; i < CF::TM; ++i)
 #pragma unroll
       for (int j = 0; j < CF::TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    if (it + 1 < niter) stash(cur ^ 1);
     __syncthreads();
   }
 #pragma unroll
@@ -222,39 +295,39 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
 }
 
 // ------------------------------------------------------------- launching
-template <class CF>
-static dim3 grid_for(int64_t M, int N, int Z) {
-  return dim3((unsigned)((M + CF::BM - 1) / CF::BM), (unsigned)((N + CF::BN - 1) / CF::BN), (unsigned)Z);
-}
-
-enum class Shape { Square, Narrow, Thin };
+enum class Shape { S96, S144, S48, S16, S64 };
 
 static Shape pick_shape(int N) {
-  if (N <= 16) return Shape::Thin;
-  const int p48 = (N + 47) / 48 * 48, p64 = (N + 63) / 64 * 64;
-  return p48 < p64 ? Shape::Narrow : Shape::Square;
+  if (N <= 16) return Shape::S16;
+  if (N <= 96) return Shape::S48;
+  if (N <= 144) return Shape::S144;
+  const int p96 = (N + 95) / 96 * 96, p64 = (N + 63) / 64 * 64;
+  return p96 <= p64 ? Shape::S96 : Shape::S64;
 }
-
-static int rows_per_block(Shape s) { return s == Shape::Thin ? 128 : 64; }
 
 template <int OP, class AL, class BL, class CS>
 static int run_gemm(AL al, BL bl, CS cs, int64_t M, int N, int K, int Z, int ksplit, dlm_precision prec,
                     hipStream_t st, Shape shape) {
   if (M <= 0 || N <= 0 || Z <= 0) return 0;
-#define DLM_LAUNCH(CFG)                                                                                   \
-  do {                                                                                                    \
-    dim3 grid = grid_for<CFG>(M, N, Z);                                                                   \
-    if (prec == DLM_BF16)                                                                                 \
-      hipLaunchKernelGGL((gemm_bf16_kernel<OP, CFG, AL, BL, CS>), grid, dim3(256), 0, st, al, bl, cs, M, N, K, \
-                         ksplit);                                                                         \
-    else                                                                                                  \
-      hipLaunchKernelGGL((gemm_f32_kernel<OP, CFG, AL, BL, CS>), grid, dim3(256), 0, st, al, bl, cs, M, N, K,  \
-                         ksplit);                                                                         \
+#define DLM_LAUNCH(CFG)                                                                                           \
+  do {                                                                                                            \
+    const int64_t nbM = (M + CFG::BM - 1) / CFG::BM;                                                              \
+    const int nbN = (N + CFG::BN - 1) / CFG::BN;                                                                  \
+    if (nbM * nbN > 0x7fffffff) return -4;                                                                        \
+    dim3 grid((unsigned)(nbM * nbN), 1, (unsigned)Z);                                                             \
+    if (prec == DLM_BF16)                                                                                         \
+      hipLaunchKernelGGL((gemm_bf16_kernel<OP, CFG, AL, BL, CS>), grid, dim3(256), 0, st, al, bl, cs, M, N, K,     \
+                         ksplit, (int)nbM, nbN);                                                                  \
+    else                                                                                                          \
+      hipLaunchKernelGGL((gemm_f32_kernel<OP, CFG, AL, BL, CS>), grid, dim3(256), 0, st, al, bl, cs, M, N, K,      \
+                         ksplit, (int)nbM, nbN);                                                                  \
   } while (0)
   switch (shape) {
-    case Shape::Thin: DLM_LAUNCH(CfgThin); break;
-    case Shape::Narrow: DLM_LAUNCH(CfgNarrow); break;
-    default: DLM_LAUNCH(CfgSquare); break;
+    case Shape::S96: DLM_LAUNCH(Cfg96); break;
+    case Shape::S144: DLM_LAUNCH(Cfg144); break;
+    case Shape::S48: DLM_LAUNCH(Cfg48); break;
+    case Shape::S16: DLM_LAUNCH(Cfg16); break;
+    default: DLM_LAUNCH(Cfg64); break;
   }
 #undef DLM_LAUNCH
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -531,7 +604,11 @@ int launch_lsc_bias_vec(const float *bias, const float *pm1, int O, int Ko, floa
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// g^T as the A operand: row m = (o,k), reduction index v; rows are contiguous.
+// Weight-gradient reduction dT[m][n] = sum_v g[v][m] * act[v][n] over voxel
+// slices (split K).  g = da_out masked by a_out > 0 (m = (o,k)); act = a_in
+// plus a ones column (n = (c,j) or n = CK, giving the bias term).  Both
+// operands are contiguous along their row index, so the voxel index is the
+// strided one.  The larger of M and N1 is put on the GEMM's row side.
 struct AGradT {
   static constexpr bool kContig = false;
   const float *g, *mask;
@@ -544,7 +621,6 @@ struct AGradT {
   }
 };
 
-// a^T plus a ones column as the B operand: column n = (c,j) or n = CK (ones).
 struct BActT {
   static constexpr bool kContig = false;
   using type = float;
@@ -553,11 +629,36 @@ struct BActT {
   __device__ float operator()(int n, int v, int) const { return n < CK ? a[(int64_t)v * CK + n] : 1.0f; }
 };
 
+// transposed orientation: activations on the row side, gradient on the column side
+struct AActT {
+  static constexpr bool kContig = false;
+  const float *a;
+  int CK;
+  __device__ float operator()(int64_t n, int v, int) const { return n < CK ? a[(int64_t)v * CK + n] : 1.0f; }
+};
+
+struct BGradT {
+  static constexpr bool kContig = false;
+  using type = float;
+  const float *g, *mask;
+  int M;
+  __device__ float operator()(int m, int v, int) const {
+    const int64_t o = (int64_t)v * M + m;
+    float x = g[o];
+    if (mask) x = mask[o] > 0.0f ? x : 0.0f;
+    return x;
+  }
+};
+
+template <bool TRANS>
 struct CPartial2 {
   float *part;
   int M, N1;
-  __device__ void operator()(int64_t m, int n, int s, float v) const {
-    part[((int64_t)s * M + m) * N1 + n] = v;
+  __device__ void operator()(int64_t r, int c, int s, float v) const {
+    if constexpr (TRANS)
+      part[((int64_t)s * M + c) * N1 + r] = v;
+    else
+      part[((int64_t)s * M + r) * N1 + c] = v;
   }
 };
 
@@ -568,9 +669,9 @@ static int split_len(int64_t K, int splits) {
 }
 
 int fold_grad_splits(int64_t V, int M, int N1) {
-  const int64_t tiles = ((M + 63) / 64) * ((N1 + 63) / 64);
-  int s = (int)std::min<int64_t>(32, std::max<int64_t>(1, (2048 + tiles - 1) / tiles));
-  s = (int)std::min<int64_t>(s, std::max<int64_t>(1, V / 256));
+  const int64_t tiles = ((std::max(M, N1) + 63) / 64) * ((std::min(M, N1) + 63) / 64);
+  int s = (int)std::min<int64_t>(64, std::max<int64_t>(1, (4096 + tiles - 1) / tiles));
+  s = (int)std::min<int64_t>(s, std::max<int64_t>(1, V / 512));
   while (s > 1 && (V + split_len(V, s) - 1) / split_len(V, s) != s) --s;
   return s;
 }
@@ -580,8 +681,12 @@ int launch_lsc_fold_grad(const float *da_out, const float *mask, const float *a_
   const int N1 = CK + 1;
   const int ks = split_len(V, splits);
   if ((V + ks - 1) / ks != splits) return -2;
-  return run_gemm<kOpFoldGrad>(AGradT{da_out, mask, M}, BActT{a_in, CK}, CPartial2{partial, M, N1}, M, N1, (int)V,
-                               splits, ks, prec, (hipStream_t)stream, pick_shape(N1));
+  hipStream_t st = (hipStream_t)stream;
+  if (M >= N1)
+    return run_gemm<kOpFoldGrad>(AGradT{da_out, mask, M}, BActT{a_in, CK}, CPartial2<false>{partial, M, N1}, M, N1,
+                                 (int)V, splits, ks, prec, st, Shape::S64);
+  return run_gemm<kOpFoldGrad>(AActT{a_in, CK}, BGradT{da_out, mask, M}, CPartial2<true>{partial, M, N1}, N1, M,
+                               (int)V, splits, ks, prec, st, Shape::S64);
 }
 
 __global__ void sum_partials_kernel(const float *part, int splits, int64_t n, float *out) {
