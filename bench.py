@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--with-copy-calibration", action="store_true",
+                    help="after the timed steps, copy a 1 GiB buffer 3 times (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -236,6 +238,14 @@ def main():
         roof_s = sum(max(v[2] / (HBM_PEAK_GBS * 1e9), v[3] / (MFMA_PEAK_TFLOPS[prec] * 1e12)) for v in rep.values())
         result["step_roofline_frac"] = round(roof_s / args.steps / (ms_step / 1e3), 4)
         result["kernels"] = kern
+    if args.with_copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes_per_dispatch"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
+        del src, dst
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, acq, args.cpu_seconds)
     print(json.dumps(result), flush=True)

@@ -120,6 +120,17 @@ dlm_status dlm_sh2signal_fwd(const dlm_sh_plan *plan, const float *c, float *x, 
 dlm_status dlm_sh2signal_bwd(const dlm_sh_plan *plan, const float *dx, float *dc, int64_t V,
                              dlm_precision prec, void *stream);
 
+/* Signal2SH straight from raw acquisitions, with the b=0 normalisation the
+ * layer requires of its input (Sec. 2.2) fused into the load:
+ *   c[v][s][:] = P_s (raw[v][dw volumes of shell s] / mean_b0(raw[v]))
+ * raw device [V][n] in the creation table's volume order (n = the table
+ * size given to dlm_sh_plan_create, b0 volumes included); the plan must have
+ * at least one b0 volume (DLM_EINVAL otherwise).  ws: device workspace of at
+ * least dlm_signal2sh_raw_workspace_bytes(V) bytes (per-voxel 1/mean_b0). */
+size_t dlm_signal2sh_raw_workspace_bytes(int64_t V);
+dlm_status dlm_signal2sh_fwd_raw(const dlm_sh_plan *plan, const float *raw, float *c, int64_t V, void *ws,
+                                 size_t ws_bytes, dlm_precision prec, void *stream);
+
 /* ------------------------------------------------------------------------
  * Local spherical convolution (Sec. 2.3, multi-b-value form Sec. 2.3.1)
  * ------------------------------------------------------------------------ */
@@ -198,6 +209,14 @@ size_t dlm_mse_workspace_bytes(int64_t n);
  * dpred device [n] = 2 (pred - target) / n (NULL to skip). */
 dlm_status dlm_mse_fwd_bwd(const float *pred, const float *target, int64_t n, float *loss, float *dpred,
                            void *ws, size_t ws_bytes, void *stream);
+
+/* A relative q-space loss (Sec. 1: once back in q-space, losses that
+ * measure the error relative to the signal become usable): loss (device
+ * scalar) = mean(((pred - target) / (|target| + eps))^2) over n elements;
+ * dpred = 2 (pred - target) / ((|target| + eps)^2 n) (NULL to skip).
+ * eps >= 0 guards near-zero targets.  Workspace as dlm_mse_fwd_bwd. */
+dlm_status dlm_relmse_fwd_bwd(const float *pred, const float *target, int64_t n, float eps, float *loss,
+                              float *dpred, void *ws, size_t ws_bytes, void *stream);
 
 /* One Adam step on n parameters (device w, g, m, v), bias-corrected with the
  * 1-based step count. */

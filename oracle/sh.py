@@ -181,3 +181,14 @@ def sh2signal_adjoint(plan: SHPlan, dx: np.ndarray) -> np.ndarray:
         out[:, s, :] = dx[:, off:off + n] @ B
         off += n
     return out
+
+
+def normalize_b0(raw: np.ndarray, bvals: np.ndarray, plan: SHPlan, b0_max: float = 50.0) -> np.ndarray:
+    """The normalisation Signal2SH requires of its input (Sec. 2.2): every
+    diffusion-weighted volume divided by the voxel's mean over the b=0
+    volumes, returned in the plan's shell-major order.  raw: (V, n_total) in
+    acquisition order."""
+    b0 = np.asarray(bvals) < b0_max
+    mean_b0 = raw[:, b0].mean(axis=1, keepdims=True)
+    order = np.concatenate(plan.shell_idx)
+    return raw[:, order] / mean_b0

@@ -23,6 +23,16 @@ def mse(pred: np.ndarray, target: np.ndarray) -> tuple[float, np.ndarray]:
     return float(np.mean(diff * diff)), 2.0 * diff / diff.size
 
 
+def relative_mse(pred: np.ndarray, target: np.ndarray, eps: float) -> tuple[float, np.ndarray]:
+    """A relative q-space loss (Sec. 1: relative losses become usable once the
+    prediction is back in q-space): each error is measured against the
+    target's magnitude, loss = mean(((pred - target) / (|target| + eps))^2);
+    dloss/dpred = 2 (pred - target) / ((|target| + eps)^2 numel)."""
+    w = 1.0 / (np.abs(target) + eps)
+    r = (pred - target) * w
+    return float(np.mean(r * r)), 2.0 * r * w / r.size
+
+
 @dataclass
 class Layer:
     plan: lsc.LSCPlan

@@ -22,7 +22,7 @@ __all__ = [
     "SHPlan", "LSCPlan", "precision_code", "signal2sh_fwd", "signal2sh_bwd", "sh2signal_fwd", "sh2signal_bwd",
     "lsc_fwd", "lsc_bwd", "lsc_workspace_bytes", "mse_fwd_bwd", "adam_step", "Workspace", "DelimitError",
     "sh_basis", "sh_fit_matrix", "lsc_kernel_points", "timing_enable", "timing_reset", "timing_report",
-    "form_code", "DEFAULT_FORM",
+    "form_code", "DEFAULT_FORM", "signal2sh_fwd_raw", "relmse_fwd_bwd",
 ]
 
 
@@ -238,6 +238,21 @@ def signal2sh_bwd(plan: SHPlan, dc: torch.Tensor, out=None, precision="fp32") ->
     return _sh_call(lib().dlm_signal2sh_bwd, plan, dc, (dc.shape[0], plan.n_dw), out, precision)
 
 
+def signal2sh_fwd_raw(plan: SHPlan, raw: torch.Tensor, out=None, precision="fp32") -> torch.Tensor:
+    """raw [V][n_total] (creation-table volume order, b0 volumes included) ->
+    c [V][S][K], with the b0 normalisation fused into the load."""
+    raw = _f32_dev(raw, "raw")
+    if raw.dim() != 2 or raw.shape[1] != plan.n_total:
+        raise ValueError(f"raw must be [V, {plan.n_total}]")
+    V = raw.shape[0]
+    if out is None:
+        out = torch.empty((V, plan.n_shells, plan.K), dtype=torch.float32, device=raw.device)
+    ws = torch.empty(lib().dlm_signal2sh_raw_workspace_bytes(V), dtype=torch.uint8, device=raw.device)
+    check(lib().dlm_signal2sh_fwd_raw(plan.handle, _ptr(raw), _ptr(out), V, _ptr(ws), ws.numel(),
+                                      precision_code(precision), _stream(raw)))
+    return out
+
+
 def sh2signal_fwd(plan: SHPlan, c: torch.Tensor, out=None, precision="fp32") -> torch.Tensor:
     """c [V][S][K] -> x [V][N_dw]."""
     if c.dim() != 3 or tuple(c.shape[1:]) != (plan.n_shells, plan.K):
@@ -318,6 +333,21 @@ def mse_fwd_bwd(pred: torch.Tensor, target: torch.Tensor, need_grad: bool = True
         dpred = torch.empty_like(pred) if need_grad else None
     check(lib().dlm_mse_fwd_bwd(_ptr(pred), _ptr(target), n, _ptr(loss), _ptr(dpred), _ptr(ws), ws.numel(),
                                 _stream(pred)))
+    return loss, dpred
+
+
+def relmse_fwd_bwd(pred: torch.Tensor, target: torch.Tensor, eps: float = 1e-3, need_grad: bool = True):
+    """(loss device scalar, dpred) for loss = mean(((pred - target) / (|target| + eps))^2)."""
+    pred = _f32_dev(pred, "pred")
+    target = _f32_dev(target, "target")
+    if pred.shape != target.shape:
+        raise ValueError("pred and target differ in shape")
+    n = pred.numel()
+    ws = torch.empty(lib().dlm_mse_workspace_bytes(n), dtype=torch.uint8, device=pred.device)
+    loss = torch.empty((), dtype=torch.float32, device=pred.device)
+    dpred = torch.empty_like(pred) if need_grad else None
+    check(lib().dlm_relmse_fwd_bwd(_ptr(pred), _ptr(target), n, float(eps), _ptr(loss), _ptr(dpred), _ptr(ws),
+                                   ws.numel(), _stream(pred)))
     return loss, dpred
 
 

@@ -98,6 +98,9 @@ struct dlm_sh_plan {
   bool uniform = true;
   // device, all shells back to back: P [S][K][N], Pt [S][N][K], B [S][N][K], Bt [S][K][N]
   DevMat dP, dPt, dB, dBt;
+  int n_b0 = 0;
+  int32_t *d_dwidx = nullptr;  // [n_dw] creation-table index of each shell-major volume
+  int32_t *d_b0idx = nullptr;  // [n_b0] creation-table indices of the b=0 volumes
   std::vector<float> stage_f;
   std::vector<uint16_t> stage_h;
   hipEvent_t staged = nullptr;
@@ -274,6 +277,21 @@ dlm_status dlm_sh_plan_create(const double *bvecs, const double *bvals, int64_t 
     if (p->dirs[s] != p->dirs[0]) p->uniform = false;
   }
   p->n_dw = off;
+  {
+    std::vector<int32_t> dw, b0;
+    for (int sh = 0; sh < p->S; ++sh)
+      for (int64_t i : p->members[sh]) dw.push_back(int32_t(i));
+    for (int64_t i = 0; i < n; ++i)
+      if (bvals[i] < b0_max) b0.push_back(int32_t(i));
+    p->n_b0 = int(b0.size());
+    if (n > int64_t(0x7fffffff) || hipMalloc(&p->d_dwidx, dw.size() * 4) != hipSuccess ||
+        hipMemcpy(p->d_dwidx, dw.data(), dw.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        (p->n_b0 > 0 && (hipMalloc(&p->d_b0idx, b0.size() * 4) != hipSuccess ||
+                         hipMemcpy(p->d_b0idx, b0.data(), b0.size() * 4, hipMemcpyHostToDevice) != hipSuccess))) {
+      dlm_sh_plan_destroy(p);
+      return fail(DLM_ENOMEM, "volume index upload failed");
+    }
+  }
   dlm_status s = sh_build_tables(p, bvecs);
   if (s == DLM_OK) s = sh_upload(p, nullptr);
   if (s == DLM_OK && hipStreamSynchronize(nullptr) != hipSuccess) s = fail(DLM_EDEVICE, "upload failed");
@@ -334,6 +352,8 @@ void dlm_sh_plan_destroy(dlm_sh_plan *p) {
   release(p->dPt);
   release(p->dB);
   release(p->dBt);
+  if (p->d_dwidx) (void)hipFree(p->d_dwidx);
+  if (p->d_b0idx) (void)hipFree(p->d_b0idx);
   delete p;
 }
 
@@ -396,6 +416,39 @@ dlm_status sh_apply(const dlm_sh_plan *p, const float *in, float *out, int64_t V
 }
 
 }  // namespace
+
+size_t dlm_signal2sh_raw_workspace_bytes(int64_t V) { return align256(size_t(std::max<int64_t>(V, 1)) * 4); }
+
+dlm_status dlm_signal2sh_fwd_raw(const dlm_sh_plan *p, const float *raw, float *c, int64_t V, void *ws,
+                                 size_t ws_bytes, dlm_precision prec, void *stream) {
+  if (!p) return fail(DLM_EINVAL, "plan is NULL");
+  if (V < 0) return fail(DLM_EINVAL, "V must be >= 0");
+  if (prec != DLM_FP32 && prec != DLM_BF16) return fail(DLM_EINVAL, "unknown precision %d", int(prec));
+  if (p->n_b0 == 0) return fail(DLM_EINVAL, "the gradient table has no b=0 volume to normalise by");
+  if (V == 0) return ok();
+  if (!raw || !c || !ws) return fail(DLM_EINVAL, "null device pointer");
+  if (ws_bytes < dlm_signal2sh_raw_workspace_bytes(V)) return fail(DLM_EWORKSPACE, "workspace too small");
+  float *inv = static_cast<float *>(ws);
+  const int K = p->K, S = p->S;
+  {
+    TimedScope ts("b0_inverse_mean", stream, double(V) * (p->n_b0 + 1) * 4.0, double(V) * p->n_b0);
+    if (launch_b0_inverse_mean(raw, p->n_total, p->d_b0idx, p->n_b0, V, inv, stream) != 0)
+      return fail(DLM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
+  }
+  const int shells = p->uniform ? 1 : S;
+  for (int s0 = 0; s0 < shells; ++s0) {
+    const int64_t N = p->dirs[s0];
+    const int64_t off = p->uniform ? 0 : p->offs[s0];
+    const int groups = p->uniform ? S : 1;
+    TimedScope ts("signal2sh_fwd_raw", stream, double(V) * groups * (double(N) + K) * 4.0,
+                  2.0 * double(V) * groups * N * K);
+    if (launch_s2sh_raw(raw, p->n_total, p->d_dwidx + off, inv, p->dP.f32 + off * K, p->dP.bf16 + off * K,
+                        c + (p->uniform ? 0 : int64_t(s0) * K), int64_t(S) * K, V, groups, int(N), K, prec,
+                        stream) != 0)
+      return fail(DLM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
+  }
+  return ok();
+}
 
 dlm_status dlm_signal2sh_fwd(const dlm_sh_plan *p, const float *x, float *c, int64_t V, dlm_precision prec, void *st) {
   return sh_apply(p, x, c, V, prec, st, ShOp::S2shFwd);
@@ -916,6 +969,18 @@ dlm_status dlm_mse_fwd_bwd(const float *pred, const float *target, int64_t n, fl
   const int nb = mse_blocks(n);
   TimedScope ts("mse", stream, double(n) * (dpred ? 12.0 : 8.0), 3.0 * double(n));
   dlm_status s = launched(launch_mse(pred, target, n, loss, dpred, static_cast<float *>(ws), nb, stream));
+  return s == DLM_OK ? ok() : s;
+}
+
+dlm_status dlm_relmse_fwd_bwd(const float *pred, const float *target, int64_t n, float eps, float *loss,
+                              float *dpred, void *ws, size_t ws_bytes, void *stream) {
+  if (n <= 0) return fail(DLM_EINVAL, "n must be > 0");
+  if (!pred || !target || !loss || !ws) return fail(DLM_EINVAL, "null device pointer");
+  if (!(eps >= 0.0f) || !std::isfinite(eps)) return fail(DLM_EINVAL, "eps must be finite and >= 0");
+  if (ws_bytes < dlm_mse_workspace_bytes(n)) return fail(DLM_EWORKSPACE, "workspace too small");
+  const int nb = mse_blocks(n);
+  TimedScope ts("relmse", stream, double(n) * (dpred ? 12.0 : 8.0), 5.0 * double(n));
+  dlm_status s = launched(launch_relmse(pred, target, n, eps, loss, dpred, static_cast<float *>(ws), nb, stream));
   return s == DLM_OK ? ok() : s;
 }
 

@@ -54,6 +54,7 @@ enum KernelOp : int {
   kOpFoldBwdData,
   kOpFoldGrad,
   kOpFoldUnfold,
+  kOpS2shRaw,
 };
 
 // C[r][n] = sum_k A[r][k] * B[n][k] over one group g:
@@ -95,6 +96,16 @@ int launch_prepare_weights(const float *W, float *Wt, uint16_t *Wh, uint16_t *Wt
                            void *stream);
 int launch_mse(const float *pred, const float *target, int64_t n, float *loss, float *dpred, float *partials,
                int nblocks, void *stream);
+// relative form: errors weighted by 1 / (|target| + eps)
+int launch_relmse(const float *pred, const float *target, int64_t n, float eps, float *loss, float *dpred,
+                  float *partials, int nblocks, void *stream);
+// inv[v] = n_b0 / sum_i raw[v*ld + b0idx[i]]
+int launch_b0_inverse_mean(const float *raw, int64_t ld, const int32_t *b0idx, int nb0, int64_t V, float *inv,
+                           void *stream);
+// Signal2SH on raw data: A(r, k) = raw[r*ld + dwidx[g*N + k]] * inv[r] for group (shell) g
+int launch_s2sh_raw(const float *raw, int64_t ld, const int32_t *dwidx, const float *inv, const float *Pf,
+                    const uint16_t *Ph, float *c, int64_t ldc, int64_t V, int S, int N, int K, dlm_precision prec,
+                    void *stream);
 int mse_blocks(int64_t n);
 int launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
                 float c1, float c2, void *stream);

@@ -45,7 +45,7 @@ using Cfg48 = Cfg<64, 48, 4, 1>;     // N <= 96 (N = 45, 90)
 using Cfg16 = Cfg<128, 16, 4, 1>;    // N <= 16
 using Cfg64 = Cfg<64, 64, 2, 2>;     // everything else
 
-// Row stride (in 32-bit words) of a k-major LDS tile whose rows hold B
+// Row stride (32-bit words) of a k-major LDS tile whose rows hold B row
 // entries: padded so that the four k-rows one MFMA operand read touches
 // start 16 banks apart (conflict-free for 32 and 64 banks).
 constexpr int lds_stride(int B) {
@@ -67,17 +67,49 @@ struct TileMap {
   }
 };
 
+__device__ __forceinline__ floatx4 ld4(const float *p) {
+  floatx4 v;
+  __builtin_memcpy(&v, p, 16);  // dword-aligned 16-byte load (global_load_dwordx4)
+  return v;
+}
+
+// Operand staging.  An operand is "k-contiguous" (kContig) or contiguous
+// along its row index.  Threads move runs of 4 elements along the
+// contiguous dimension: op.load4(row, k, g) for a run that lies inside the
+// matrix, element-wise op(row, k, g) with zero fill at ragged edges.
+template <class OPND, int ROWS, int BK>
+struct Runs {
+  static constexpr bool KC = OPND::kContig;
+  static constexpr int NRUN = ROWS * BK / 4;               // runs per tile
+  static constexpr int PER = (NRUN + 255) / 256;            // runs per thread
+  __device__ static void coord(int e, int &row, int &k) {
+    if constexpr (KC) { k = 4 * (e % (BK / 4)); row = e / (BK / 4); } else { row = 4 * (e % (ROWS / 4)); k = e / (ROWS / 4); }
+  }
+};
+
 // ------------------------------------------------------------- FP32 core
+// LDS: a k-contiguous operand is stored row-major with k contiguous (row
+// stride BK+4 words) and each lane reads 4 consecutive k with one 128-bit
+// LDS load; a row-contiguous operand is stored k-major (rows contiguous)
+// and read one word per MFMA.  Both use the same k order inside a 16-wide
+// slice: MFMA j of 4 takes k = 4*(lane/16) + j, which is a permutation of
+// the reduction index applied identically to A and B.
 template <int OP, class CF, class AL, class BL, class CS>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(AL al, BL bl, CS cs, int64_t M, int N, int K, int ksplit,
                                                        int nbM, int nbN) {
   constexpr int BM = CF::BM, BN = CF::BN, BK = 16;
-  constexpr int SA = lds_stride(BM), SB = lds_stride(BN);
-  constexpr int APT = BM * BK / 256, BPT = (BN * BK + 255) / 256;
-  __shared__ float As[2][BK * SA];
-  __shared__ float Bs[2][BK * SB];
+  constexpr bool AK = AL::kContig, BKC = BL::kContig;
+  constexpr int SA = AK ? BK + 4 : lds_stride(BM);
+  constexpr int SB = BKC ? BK + 4 : lds_stride(BN);
+  constexpr int AE = AK ? BM * SA : BK * SA;
+  constexpr int BE = BKC ? BN * SB : BK * SB;
+  using RA = Runs<AL, BM, BK>;
+  using RB = Runs<BL, BN, BK>;
+  __shared__ __attribute__((aligned(16))) float As[2][AE];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % CF::WM, wn = wave / CF::WM;
+  const int q16 = lane & 15, g4 = lane >> 4;
   const TileMap tm(blockIdx.x, nbM, nbN);
   const int64_t m0 = (int64_t)tm.mt * BM;
   const int n0 = tm.nt * BN;
@@ -87,41 +119,87 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(AL al, BL bl, CS cs, int6
     kbeg = g * ksplit;
     kend = min(K, kbeg + ksplit);
   }
-  float ra[APT], rb[BPT];
+  floatx4 ra[RA::PER], rb[RB::PER];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int p = 0; p < APT; ++p) {
+    for (int p = 0; p < RA::PER; ++p) {
       const int e = tid + p * 256;
-      int mm, kk;
-      if constexpr (AL::kContig) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
-      const int64_t r = m0 + mm;
-      const int k = k0 + kk;
-      ra[p] = (r < M && k < kend) ? al(r, k, g) : 0.0f;
+      int row, kk;
+      RA::coord(e, row, kk);
+      if (e < RA::NRUN) {
+        const int64_t r = m0 + row;
+        const int k = k0 + kk;
+        if constexpr (AK) {
+          if (r < M && k + 3 < kend) ra[p] = al.load4(r, k, g);
+          else {
+            floatx4 v = {0.f, 0.f, 0.f, 0.f};
+            if (r < M)
+              for (int i = 0; i < 4; ++i)
+                if (k + i < kend) v[i] = al(r, k + i, g);
+            ra[p] = v;
+          }
+        } else {
+          if (r + 3 < M && k < kend) ra[p] = al.load4(r, k, g);
+          else {
+            floatx4 v = {0.f, 0.f, 0.f, 0.f};
+            if (k < kend)
+              for (int i = 0; i < 4; ++i)
+                if (r + i < M) v[i] = al(r + i, k, g);
+            ra[p] = v;
+          }
+        }
+      }
     }
 #pragma unroll
-    for (int p = 0; p < BPT; ++p) {
+    for (int p = 0; p < RB::PER; ++p) {
       const int e = tid + p * 256;
-      int nn, kk;
-      if constexpr (BL::kContig) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
-      const int n = n0 + nn;
-      const int k = k0 + kk;
-      rb[p] = (e < BN * BK && n < N && k < kend) ? bl(n, k, g) : 0.0f;
+      int col, kk;
+      RB::coord(e, col, kk);
+      if (e < RB::NRUN) {
+        const int n = n0 + col;
+        const int k = k0 + kk;
+        if constexpr (BKC) {
+          if (n < N && k + 3 < kend) rb[p] = bl.load4(n, k, g);
+          else {
+            floatx4 v = {0.f, 0.f, 0.f, 0.f};
+            if (n < N)
+              for (int i = 0; i < 4; ++i)
+                if (k + i < kend) v[i] = bl(n, k + i, g);
+            rb[p] = v;
+          }
+        } else {
+          if (n + 3 < N && k < kend) rb[p] = bl.load4(n, k, g);
+          else {
+            floatx4 v = {0.f, 0.f, 0.f, 0.f};
+            if (k < kend)
+              for (int i = 0; i < 4; ++i)
+                if (n + i < N) v[i] = bl(n + i, k, g);
+            rb[p] = v;
+          }
+        }
+      }
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
-    for (int p = 0; p < APT; ++p) {
+    for (int p = 0; p < RA::PER; ++p) {
       const int e = tid + p * 256;
-      int mm, kk;
-      if constexpr (AL::kContig) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
-      As[buf][kk * SA + mm] = ra[p];
+      int row, kk;
+      RA::coord(e, row, kk);
+      if (e < RA::NRUN) {
+        if constexpr (AK) *reinterpret_cast<floatx4 *>(&As[buf][row * SA + kk]) = ra[p];
+        else *reinterpret_cast<floatx4 *>(&As[buf][kk * SA + row]) = ra[p];
+      }
     }
 #pragma unroll
-    for (int p = 0; p < BPT; ++p) {
+    for (int p = 0; p < RB::PER; ++p) {
       const int e = tid + p * 256;
-      int nn, kk;
-      if constexpr (BL::kContig) { kk = e % BK; nn = e / BK; } else { nn = e % BN; kk = e / BN; }
-      if (e < BN * BK) Bs[buf][kk * SB + nn] = rb[p];
+      int col, kk;
+      RB::coord(e, col, kk);
+      if (e < RB::NRUN) {
+        if constexpr (BKC) *reinterpret_cast<floatx4 *>(&Bs[buf][col * SB + kk]) = rb[p];
+        else *reinterpret_cast<floatx4 *>(&Bs[buf][kk * SB + col]) = rb[p];
+      }
     }
   };
   floatx4 acc[CF::TM][CF::TN];
@@ -141,19 +219,28 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(AL al, BL bl, CS cs, int6
     if (it + 1 < niter) load(kbeg + (it + 1) * BK);
     const float *Ac = As[cur];
     const float *Bc = Bs[cur];
+    floatx4 a[CF::TM], b[CF::TN];
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      float a[CF::TM], b[CF::TN];
-      const int row = kk + (lane >> 4);
+    for (int i = 0; i < CF::TM; ++i) {
+      const int row = (wm * CF::TM + i) * 16 + q16;
+      if constexpr (AK) a[i] = *reinterpret_cast<const floatx4 *>(&Ac[row * SA + 4 * g4]);
+      else
+        for (int j = 0; j < 4; ++j) a[i][j] = Ac[(4 * g4 + j) * SA + row];
+    }
 #pragma unroll
-      for (int i = 0; i < CF::TM; ++i) a[i] = Ac[row * SA + (wm * CF::TM + i) * 16 + (lane & 15)];
+    for (int jn = 0; jn < CF::TN; ++jn) {
+      const int col = (wn * CF::TN + jn) * 16 + q16;
+      if constexpr (BKC) b[jn] = *reinterpret_cast<const floatx4 *>(&Bc[col * SB + 4 * g4]);
+      else
+        for (int j = 0; j < 4; ++j) b[jn][j] = Bc[(4 * g4 + j) * SB + col];
+    }
 #pragma unroll
-      for (int j = 0; j < CF::TN; ++j) b[j] = Bc[row * SB + (wn * CF::TN + j) * 16 + (lane & 15)];
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int i = 0; i < CF::TM; ++i)
 #pragma unroll
-        for (int j = 0; j < CF::TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
+        for (int jn = 0; jn < CF::TN; ++jn)
+          acc[i][jn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][j], b[jn][j], acc[i][jn], 0, 0, 0);
     if (it + 1 < niter) stash(cur ^ 1);
     __syncthreads();
   }
@@ -163,24 +250,38 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(AL al, BL bl, CS cs, int6
     for (int j = 0; j < CF::TN; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int64_t r = m0 + (wm * CF::TM + i) * 16 + 4 * (lane >> 4) + q;
-        const int n = n0 + (wn * CF::TN + j) * 16 + (lane & 15);
+        const int64_t r = m0 + (wm * CF::TM + i) * 16 + 4 * g4 + q;
+        const int n = n0 + (wn * CF::TN + j) * 16 + q16;
         if (r < M && n < N) cs(r, n, g, acc[i][j][q]);
       }
 }
 
 // ------------------------------------------------------------- BF16 core
-// LDS holds m-major rows of BK bfloat16 (k contiguous) so that each lane
-// reads its 8 consecutive k as one 16-byte load.
+// LDS holds both operands row-major with BK bfloat16 per row (k
+// contiguous, row stride BK+8) so each lane reads its 8 consecutive k with
+// one 128-bit load.  k-contiguous operands arrive as runs of 4 k (one
+// 64-bit LDS store after conversion); row-contiguous operands arrive as 4
+// rows x 2 consecutive k (four 32-bit stores of bf16 pairs).
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+  return (uint32_t)to_bf16_bits(lo) | ((uint32_t)to_bf16_bits(hi) << 16);
+}
+
 template <int OP, class CF, class AL, class BL, class CS>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int64_t M, int N, int K, int ksplit,
                                                         int nbM, int nbN) {
   constexpr int BM = CF::BM, BN = CF::BN, BK = 32, LD = BK + 8;
-  constexpr int APT = BM * BK / 256, BPT = (BN * BK + 255) / 256;
+  constexpr bool AK = AL::kContig, BKC = BL::kContig;
+  constexpr bool BT = std::is_same<typename BL::type, uint16_t>::value;
+  static_assert(!BT || BKC, "bfloat16 tables are k-contiguous");
+  // items per tile: k-contiguous -> runs of 4 k; row-contiguous -> 4 rows x 2 k
+  constexpr int NA = AK ? BM * BK / 4 : (BM / 4) * (BK / 2);
+  constexpr int NB = BKC ? BN * BK / 4 : (BN / 4) * (BK / 2);
+  constexpr int PA = (NA + 255) / 256, PB = (NB + 255) / 256;
   __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LD];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % CF::WM, wn = wave / CF::WM;
+  const int q16 = lane & 15, g4 = lane >> 4;
   const TileMap tm(blockIdx.x, nbM, nbN);
   const int64_t m0 = (int64_t)tm.mt * BM;
   const int n0 = tm.nt * BN;
@@ -190,67 +291,117 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
     kbeg = g * ksplit;
     kend = min(K, kbeg + ksplit);
   }
-  // K-contiguous operands: each thread converts pairs of consecutive k and
-  // stores them as one 32-bit word.
-  uint32_t ra[APT], rb[BPT];
-  // Every thread converts pairs of consecutive k and stores them as one
-  // 32-bit LDS word; for m/n-contiguous operands the pair's two loads are
-  // each coalesced across the consecutive m (n) of neighbouring threads.
-  auto ida = [&](int e, int &mm, int &kk) {
-    if constexpr (AL::kContig) { kk = 2 * (e % (BK / 2)); mm = e / (BK / 2); } else { mm = e % BM; kk = 2 * (e / BM); }
+  // register staging: k-contiguous items need 2 words, row-contiguous 4
+  uint32_t ra[PA][AK ? 2 : 4], rb[PB][BKC ? 2 : 4];
+  auto coordA = [&](int e, int &row, int &kk) {
+    if constexpr (AK) { kk = 4 * (e % (BK / 4)); row = e / (BK / 4); } else { row = 4 * (e % (BM / 4)); kk = 2 * (e / (BM / 4)); }
   };
-  auto idb = [&](int e, int &nn, int &kk) {
-    if constexpr (BL::kContig) { kk = 2 * (e % (BK / 2)); nn = e / (BK / 2); } else { nn = e % BN; kk = 2 * (e / BN); }
+  auto coordB = [&](int e, int &col, int &kk) {
+    if constexpr (BKC) { kk = 4 * (e % (BK / 4)); col = e / (BK / 4); } else { col = 4 * (e % (BN / 4)); kk = 2 * (e / (BN / 4)); }
   };
-  constexpr int AITEMS = APT / 2;
-  constexpr int BITEMS = (BPT + 1) / 2;
-  constexpr int BTOTAL = BN * BK / 2;
-  auto cvt = [&](float f) -> uint32_t { return (uint32_t)to_bf16_bits(f); };
   auto load = [&](int k0) {
 #pragma unroll
-    for (int p = 0; p < AITEMS; ++p) {
+    for (int p = 0; p < PA; ++p) {
       const int e = tid + p * 256;
-      int mm, kk;
-      ida(e, mm, kk);
-      const int64_t r = m0 + mm;
+      if (e >= NA) continue;
+      int row, kk;
+      coordA(e, row, kk);
+      const int64_t r = m0 + row;
       const int k = k0 + kk;
-      const uint32_t lo = (r < M && k < kend) ? cvt(al(r, k, g)) : 0u;
-      const uint32_t hi = (r < M && k + 1 < kend) ? cvt(al(r, k + 1, g)) : 0u;
-      ra[p] = lo | (hi << 16);
+      if constexpr (AK) {
+        floatx4 v = {0.f, 0.f, 0.f, 0.f};
+        if (r < M && k + 3 < kend) v = al.load4(r, k, g);
+        else if (r < M)
+          for (int i = 0; i < 4; ++i)
+            if (k + i < kend) v[i] = al(r, k + i, g);
+        ra[p][0] = pack_bf16(v[0], v[1]);
+        ra[p][1] = pack_bf16(v[2], v[3]);
+      } else {
+        floatx4 v0 = {0.f, 0.f, 0.f, 0.f}, v1 = {0.f, 0.f, 0.f, 0.f};
+        if (r + 3 < M) {
+          if (k < kend) v0 = al.load4(r, k, g);
+          if (k + 1 < kend) v1 = al.load4(r, k + 1, g);
+        } else {
+          for (int i = 0; i < 4; ++i)
+            if (r + i < M) {
+              if (k < kend) v0[i] = al(r + i, k, g);
+              if (k + 1 < kend) v1[i] = al(r + i, k + 1, g);
+            }
+        }
+        for (int i = 0; i < 4; ++i) ra[p][i] = pack_bf16(v0[i], v1[i]);
+      }
     }
 #pragma unroll
-    for (int p = 0; p < BITEMS; ++p) {
+    for (int p = 0; p < PB; ++p) {
       const int e = tid + p * 256;
-      int nn, kk;
-      idb(e, nn, kk);
-      const int n = n0 + nn;
+      if (e >= NB) continue;
+      int col, kk;
+      coordB(e, col, kk);
+      const int n = n0 + col;
       const int k = k0 + kk;
-      const bool okn = e < BTOTAL && n < N;
-      uint32_t lo = 0u, hi = 0u;
-      if constexpr (std::is_same<typename BL::type, float>::value) {
-        lo = (okn && k < kend) ? cvt(bl(n, k, g)) : 0u;
-        hi = (okn && k + 1 < kend) ? cvt(bl(n, k + 1, g)) : 0u;
+      if constexpr (BT) {
+        uint32_t w0 = 0u, w1 = 0u;
+        if (n < N && k + 3 < kend) {
+          const uint2 h = bl.load4h(n, k, g);
+          w0 = h.x;
+          w1 = h.y;
+        } else if (n < N) {
+          uint32_t h[4] = {0u, 0u, 0u, 0u};
+          for (int i = 0; i < 4; ++i)
+            if (k + i < kend) h[i] = bl(n, k + i, g);
+          w0 = h[0] | (h[1] << 16);
+          w1 = h[2] | (h[3] << 16);
+        }
+        rb[p][0] = w0;
+        rb[p][1] = w1;
+      } else if constexpr (BKC) {
+        floatx4 v = {0.f, 0.f, 0.f, 0.f};
+        if (n < N && k + 3 < kend) v = bl.load4(n, k, g);
+        else if (n < N)
+          for (int i = 0; i < 4; ++i)
+            if (k + i < kend) v[i] = bl(n, k + i, g);
+        rb[p][0] = pack_bf16(v[0], v[1]);
+        rb[p][1] = pack_bf16(v[2], v[3]);
       } else {
-        lo = (okn && k < kend) ? (uint32_t)bl(n, k, g) : 0u;
-        hi = (okn && k + 1 < kend) ? (uint32_t)bl(n, k + 1, g) : 0u;
+        floatx4 v0 = {0.f, 0.f, 0.f, 0.f}, v1 = {0.f, 0.f, 0.f, 0.f};
+        if (n + 3 < N) {
+          if (k < kend) v0 = bl.load4(n, k, g);
+          if (k + 1 < kend) v1 = bl.load4(n, k + 1, g);
+        } else {
+          for (int i = 0; i < 4; ++i)
+            if (n + i < N) {
+              if (k < kend) v0[i] = bl(n + i, k, g);
+              if (k + 1 < kend) v1[i] = bl(n + i, k + 1, g);
+            }
+        }
+        for (int i = 0; i < 4; ++i) rb[p][i] = pack_bf16(v0[i], v1[i]);
       }
-      rb[p] = lo | (hi << 16);
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
-    for (int p = 0; p < AITEMS; ++p) {
+    for (int p = 0; p < PA; ++p) {
       const int e = tid + p * 256;
-      int mm, kk;
-      ida(e, mm, kk);
-      *reinterpret_cast<uint32_t *>(&As[buf][mm * LD + kk]) = ra[p];
+      if (e >= NA) continue;
+      int row, kk;
+      coordA(e, row, kk);
+      if constexpr (AK) {
+        *reinterpret_cast<uint2 *>(&As[buf][row * LD + kk]) = make_uint2(ra[p][0], ra[p][1]);
+      } else {
+        for (int i = 0; i < 4; ++i) *reinterpret_cast<uint32_t *>(&As[buf][(row + i) * LD + kk]) = ra[p][i];
+      }
     }
 #pragma unroll
-    for (int p = 0; p < BITEMS; ++p) {
+    for (int p = 0; p < PB; ++p) {
       const int e = tid + p * 256;
-      int nn, kk;
-      idb(e, nn, kk);
-      if (e < BTOTAL) *reinterpret_cast<uint32_t *>(&Bs[buf][nn * LD + kk]) = rb[p];
+      if (e >= NB) continue;
+      int col, kk;
+      coordB(e, col, kk);
+      if constexpr (BKC) {
+        *reinterpret_cast<uint2 *>(&Bs[buf][col * LD + kk]) = make_uint2(rb[p][0], rb[p][1]);
+      } else {
+        for (int i = 0; i < 4; ++i) *reinterpret_cast<uint32_t *>(&Bs[buf][(col + i) * LD + kk]) = rb[p][i];
+      }
     }
   };
   floatx4 acc[CF::TM][CF::TN];
@@ -271,10 +422,10 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
     bf16x8 a[CF::TM], b[CF::TN];
 #pragma unroll
     for (int i = 0; i < CF::TM; ++i)
-      a[i] = *reinterpret_cast<const bf16x8 *>(&As[cur][((wm * CF::TM + i) * 16 + (lane & 15)) * LD + 8 * (lane >> 4)]);
+      a[i] = *reinterpret_cast<const bf16x8 *>(&As[cur][((wm * CF::TM + i) * 16 + q16) * LD + 8 * g4]);
 #pragma unroll
     for (int j = 0; j < CF::TN; ++j)
-      b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[cur][((wn * CF::TN + j) * 16 + (lane & 15)) * LD + 8 * (lane >> 4)]);
+      b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[cur][((wn * CF::TN + j) * 16 + q16) * LD + 8 * g4]);
 #pragma unroll
     for (int i = 0; i < CF::TM; ++i)
 #pragma unroll
@@ -288,8 +439,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
     for (int j = 0; j < CF::TN; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int64_t r = m0 + (wm * CF::TM + i) * 16 + 4 * (lane >> 4) + q;
-        const int n = n0 + (wn * CF::TN + j) * 16 + (lane & 15);
+        const int64_t r = m0 + (wm * CF::TM + i) * 16 + 4 * g4 + q;
+        const int n = n0 + (wn * CF::TN + j) * 16 + q16;
         if (r < M && n < N) cs(r, n, g, acc[i][j][q]);
       }
 }
@@ -305,22 +456,22 @@ static Shape pick_shape(int N) {
   return p96 <= p64 ? Shape::S96 : Shape::S64;
 }
 
-template <int OP, class AL, class BL, class CS>
-static int run_gemm(AL al, BL bl, CS cs, int64_t M, int N, int K, int Z, int ksplit, dlm_precision prec,
-                    hipStream_t st, Shape shape) {
+// Launch only the kernel of the requested precision (BF16 = true).
+template <int OP, bool BF16, class AL, class BL, class CS>
+static int run_gemm_p(AL al, BL bl, CS cs, int64_t M, int N, int K, int Z, int ksplit, hipStream_t st, Shape shape) {
   if (M <= 0 || N <= 0 || Z <= 0) return 0;
-#define DLM_LAUNCH(CFG)                                                                                           \
-  do {                                                                                                            \
-    const int64_t nbM = (M + CFG::BM - 1) / CFG::BM;                                                              \
-    const int nbN = (N + CFG::BN - 1) / CFG::BN;                                                                  \
-    if (nbM * nbN > 0x7fffffff) return -4;                                                                        \
-    dim3 grid((unsigned)(nbM * nbN), 1, (unsigned)Z);                                                             \
-    if (prec == DLM_BF16)                                                                                         \
-      hipLaunchKernelGGL((gemm_bf16_kernel<OP, CFG, AL, BL, CS>), grid, dim3(256), 0, st, al, bl, cs, M, N, K,     \
-                         ksplit, (int)nbM, nbN);                                                                  \
-    else                                                                                                          \
-      hipLaunchKernelGGL((gemm_f32_kernel<OP, CFG, AL, BL, CS>), grid, dim3(256), 0, st, al, bl, cs, M, N, K,      \
-                         ksplit, (int)nbM, nbN);                                                                  \
+#define DLM_LAUNCH(CFG)                                                                                          \
+  do {                                                                                                           \
+    const int64_t nbM = (M + CFG::BM - 1) / CFG::BM;                                                             \
+    const int nbN = (N + CFG::BN - 1) / CFG::BN;                                                                 \
+    if (nbM * nbN > 0x7fffffff) return -4;                                                                       \
+    dim3 grid((unsigned)(nbM * nbN), 1, (unsigned)Z);                                                            \
+    if constexpr (BF16)                                                                                          \
+      hipLaunchKernelGGL((gemm_bf16_kernel<OP, CFG, AL, BL, CS>), grid, dim3(256), 0, st, al, bl, cs, M, N, K,    \
+                         ksplit, (int)nbM, nbN);                                                                 \
+    else                                                                                                         \
+      hipLaunchKernelGGL((gemm_f32_kernel<OP, CFG, AL, BL, CS>), grid, dim3(256), 0, st, al, bl, cs, M, N, K,     \
+                         ksplit, (int)nbM, nbN);                                                                 \
   } while (0)
   switch (shape) {
     case Shape::S96: DLM_LAUNCH(Cfg96); break;
@@ -331,6 +482,13 @@ static int run_gemm(AL al, BL bl, CS cs, int64_t M, int N, int K, int Z, int ksp
   }
 #undef DLM_LAUNCH
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int OP, class AL, class BL, class CS>
+static int run_gemm(AL al, BL bl, CS cs, int64_t M, int N, int K, int Z, int ksplit, dlm_precision prec,
+                    hipStream_t st, Shape shape) {
+  if (prec == DLM_BF16) return run_gemm_p<OP, true>(al, bl, cs, M, N, K, Z, ksplit, st, shape);
+  return run_gemm_p<OP, false>(al, bl, cs, M, N, K, Z, ksplit, st, shape);
 }
 
 // ------------------------------------------------------- operand policies
@@ -344,6 +502,15 @@ struct ARowMajor {
     if (mask) v = mask[o] > 0.0f ? v : 0.0f;
     return v;
   }
+  __device__ floatx4 load4(int64_t r, int k, int g) const {
+    const int64_t o = r * lda + (int64_t)g * gs + k;
+    floatx4 v = ld4(A + o);
+    if (mask) {
+      const floatx4 m = ld4(mask + o);
+      for (int i = 0; i < 4; ++i) v[i] = m[i] > 0.0f ? v[i] : 0.0f;
+    }
+    return v;
+  }
 };
 
 struct BTableF {
@@ -353,6 +520,7 @@ struct BTableF {
   int64_t gs;
   int K;
   __device__ float operator()(int n, int k, int g) const { return B[(int64_t)g * gs + (int64_t)n * K + k]; }
+  __device__ floatx4 load4(int n, int k, int g) const { return ld4(B + (int64_t)g * gs + (int64_t)n * K + k); }
 };
 
 struct BTableH {
@@ -362,6 +530,11 @@ struct BTableH {
   int64_t gs;
   int K;
   __device__ uint16_t operator()(int n, int k, int g) const { return B[(int64_t)g * gs + (int64_t)n * K + k]; }
+  __device__ uint2 load4h(int n, int k, int g) const {
+    uint2 v;
+    __builtin_memcpy(&v, B + (int64_t)g * gs + (int64_t)n * K + k, 8);
+    return v;
+  }
 };
 
 struct CRowMajor {
@@ -381,8 +554,8 @@ static int table_gemm_op(const TableGemm &t, dlm_precision prec, hipStream_t st)
   const Shape sh = pick_shape(t.N);
   CRowMajor cs{t.C, t.ldc, t.c_gs, t.relu, t.bias_n};
   ARowMajor al{t.A, t.mask, t.lda, t.a_gs};
-  if (prec == DLM_BF16) return run_gemm<OP>(al, BTableH{t.Bh, t.b_gs, t.K}, cs, t.M, t.N, t.K, t.groups, 0, prec, st, sh);
-  return run_gemm<OP>(al, BTableF{t.Bf, t.b_gs, t.K}, cs, t.M, t.N, t.K, t.groups, 0, prec, st, sh);
+  if (prec == DLM_BF16) return run_gemm_p<OP, true>(al, BTableH{t.Bh, t.b_gs, t.K}, cs, t.M, t.N, t.K, t.groups, 0, st, sh);
+  return run_gemm_p<OP, false>(al, BTableF{t.Bf, t.b_gs, t.K}, cs, t.M, t.N, t.K, t.groups, 0, st, sh);
 }
 
 int launch_table_gemm(const TableGemm &t, dlm_precision prec, void *stream) {
@@ -415,6 +588,9 @@ struct ANbhd {
     const int64_t P = (int64_t)m * T;
     return X[(v * C + c) * P + (int64_t)i * T + t];
   }
+  __device__ floatx4 load4(int64_t r, int k, int g) const {
+    return floatx4{(*this)(r, k, g), (*this)(r, k + 1, g), (*this)(r, k + 2, g), (*this)(r, k + 3, g)};
+  }
 };
 
 struct BWeightF {
@@ -423,6 +599,7 @@ struct BWeightF {
   const float *W;
   int ld;
   __device__ float operator()(int n, int k, int) const { return W[(int64_t)n * ld + k]; }
+  __device__ floatx4 load4(int n, int k, int) const { return ld4(W + (int64_t)n * ld + k); }
 };
 
 struct BWeightH {
@@ -431,6 +608,11 @@ struct BWeightH {
   const uint16_t *W;
   int ld;
   __device__ uint16_t operator()(int n, int k, int) const { return W[(int64_t)n * ld + k]; }
+  __device__ uint2 load4h(int n, int k, int) const {
+    uint2 v;
+    __builtin_memcpy(&v, W + (int64_t)n * ld + k, 8);
+    return v;
+  }
 };
 
 struct CSignalY {
@@ -453,8 +635,8 @@ int launch_lsc_contract_fwd(const float *X, const float *W, const uint16_t *Wh, 
   ANbhd al{X, m, T, C};
   CSignalY cs{y, bias, m, O};
   const Shape sh = pick_shape(O);
-  if (prec == DLM_BF16) return run_gemm<kOpContractFwd>(al, BWeightH{Wh, K}, cs, M, O, K, 1, 0, prec, st, sh);
-  return run_gemm<kOpContractFwd>(al, BWeightF{W, K}, cs, M, O, K, 1, 0, prec, st, sh);
+  if (prec == DLM_BF16) return run_gemm_p<kOpContractFwd, true>(al, BWeightH{Wh, K}, cs, M, O, K, 1, 0, st, sh);
+  return run_gemm_p<kOpContractFwd, false>(al, BWeightF{W, K}, cs, M, O, K, 1, 0, st, sh);
 }
 
 // dy as the A operand: row r = (v, i), column k = o; consecutive rows are
@@ -467,6 +649,9 @@ struct ADy {
     const int64_t v = r / m;
     const int i = (int)(r - v * m);
     return dy[(v * O + o) * m + i];
+  }
+  __device__ floatx4 load4(int64_t r, int o, int g) const {
+    return floatx4{(*this)(r, o, g), (*this)(r + 1, o, g), (*this)(r + 2, o, g), (*this)(r + 3, o, g)};
   }
 };
 
@@ -490,8 +675,8 @@ int launch_lsc_contract_bwd_data(const float *dy, const float *Wt, const uint16_
   ADy al{dy, m, O};
   CNbhd cs{dX, m, T, C};
   const Shape sh = pick_shape(N);
-  if (prec == DLM_BF16) return run_gemm<kOpContractBwdData>(al, BWeightH{Wth, O}, cs, M, N, O, 1, 0, prec, st, sh);
-  return run_gemm<kOpContractBwdData>(al, BWeightF{Wt, O}, cs, M, N, O, 1, 0, prec, st, sh);
+  if (prec == DLM_BF16) return run_gemm_p<kOpContractBwdData, true>(al, BWeightH{Wth, O}, cs, M, N, O, 1, 0, st, sh);
+  return run_gemm_p<kOpContractBwdData, false>(al, BWeightF{Wt, O}, cs, M, N, O, 1, 0, st, sh);
 }
 
 // Weight gradient: rows r = (c, t) plus one bias row (r = C*T, value 1),
@@ -508,6 +693,9 @@ struct AXt {
     const int64_t P = (int64_t)m * T;
     return X[((int64_t)v * C + c) * P + (int64_t)i * T + t];
   }
+  __device__ floatx4 load4(int64_t r, int k, int g) const {
+    return floatx4{(*this)(r, k, g), (*this)(r + 1, k, g), (*this)(r + 2, k, g), (*this)(r + 3, k, g)};
+  }
 };
 
 struct BDyT {
@@ -518,6 +706,9 @@ struct BDyT {
   __device__ float operator()(int o, int k, int) const {
     const int v = k / m, i = k - v * m;
     return dy[((int64_t)v * O + o) * m + i];
+  }
+  __device__ floatx4 load4(int o, int k, int g) const {
+    return floatx4{(*this)(o, k, g), (*this)(o, k + 1, g), (*this)(o, k + 2, g), (*this)(o, k + 3, g)};
   }
 };
 
@@ -566,6 +757,7 @@ struct BQt {
   const float *Q;
   int KK;
   __device__ float operator()(int n, int t, int) const { return Q[(int64_t)t * KK + n]; }
+  __device__ floatx4 load4(int n, int t, int) const { return ld4(Q + (int64_t)t * KK + n); }
 };
 
 struct CFold {
@@ -619,6 +811,15 @@ struct AGradT {
     if (mask) x = mask[o] > 0.0f ? x : 0.0f;
     return x;
   }
+  __device__ floatx4 load4(int64_t m, int v, int) const {
+    const int64_t o = (int64_t)v * M + m;
+    floatx4 x = ld4(g + o);
+    if (mask) {
+      const floatx4 k = ld4(mask + o);
+      for (int i = 0; i < 4; ++i) x[i] = k[i] > 0.0f ? x[i] : 0.0f;
+    }
+    return x;
+  }
 };
 
 struct BActT {
@@ -627,6 +828,10 @@ struct BActT {
   const float *a;
   int CK;
   __device__ float operator()(int n, int v, int) const { return n < CK ? a[(int64_t)v * CK + n] : 1.0f; }
+  __device__ floatx4 load4(int n, int v, int g) const {
+    if (n + 3 < CK) return ld4(a + (int64_t)v * CK + n);
+    return floatx4{(*this)(n, v, g), (*this)(n + 1, v, g), (*this)(n + 2, v, g), (*this)(n + 3, v, g)};
+  }
 };
 
 // transposed orientation: activations on the row side, gradient on the column side
@@ -635,6 +840,10 @@ struct AActT {
   const float *a;
   int CK;
   __device__ float operator()(int64_t n, int v, int) const { return n < CK ? a[(int64_t)v * CK + n] : 1.0f; }
+  __device__ floatx4 load4(int64_t n, int v, int g) const {
+    if (n + 3 < CK) return ld4(a + (int64_t)v * CK + n);
+    return floatx4{(*this)(n, v, g), (*this)(n + 1, v, g), (*this)(n + 2, v, g), (*this)(n + 3, v, g)};
+  }
 };
 
 struct BGradT {
@@ -646,6 +855,15 @@ struct BGradT {
     const int64_t o = (int64_t)v * M + m;
     float x = g[o];
     if (mask) x = mask[o] > 0.0f ? x : 0.0f;
+    return x;
+  }
+  __device__ floatx4 load4(int m, int v, int) const {
+    const int64_t o = (int64_t)v * M + m;
+    floatx4 x = ld4(g + o);
+    if (mask) {
+      const floatx4 k = ld4(mask + o);
+      for (int i = 0; i < 4; ++i) x[i] = k[i] > 0.0f ? x[i] : 0.0f;
+    }
     return x;
   }
 };
@@ -713,6 +931,9 @@ struct AUnfold {
     const int kk = k / Ki, j = k - kk * Ki;
     return dTw[((int64_t)o * Ko + kk) * N1 + (int64_t)c * Ki + j];
   }
+  __device__ floatx4 load4(int64_t r, int k, int g) const {
+    return floatx4{(*this)(r, k, g), (*this)(r, k + 1, g), (*this)(r, k + 2, g), (*this)(r, k + 3, g)};
+  }
 };
 
 __global__ void bias_grad_kernel(const float *dTw, const float *pm1, int O, int Ko, int N1, int CK, float *db) {
@@ -779,15 +1000,19 @@ int launch_prepare_weights(const float *W, float *Wt, uint16_t *Wh, uint16_t *Wt
 }
 
 // MSE: each block sums its grid-stride share in a fixed order and writes one
-// partial; a single block then adds the partials in index order.
+// partial; a single block then adds the partials in index order.  REL
+// weights every error by 1 / (|target| + eps).
+template <bool REL>
 __global__ __launch_bounds__(256) void mse_partial_kernel(const float *pred, const float *target, int64_t n,
-                                                          float *dpred, float *partials, float scale) {
+                                                          float *dpred, float *partials, float scale, float eps) {
   __shared__ float red[256];
   float s = 0.0f;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const float d = pred[i] - target[i];
+    const float t = target[i];
+    const float w = REL ? 1.0f / (fabsf(t) + eps) : 1.0f;
+    const float d = (pred[i] - t) * w;
     s += d * d;
-    if (dpred) dpred[i] = scale * d;
+    if (dpred) dpred[i] = scale * d * w;
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -821,10 +1046,60 @@ int mse_blocks(int64_t n) {
 int launch_mse(const float *pred, const float *target, int64_t n, float *loss, float *dpred, float *partials,
                int nblocks, void *stream) {
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(mse_partial_kernel, dim3(nblocks), dim3(256), 0, st, pred, target, n, dpred, partials,
-                     (float)(2.0 / (double)n));
+  hipLaunchKernelGGL(mse_partial_kernel<false>, dim3(nblocks), dim3(256), 0, st, pred, target, n, dpred, partials,
+                     (float)(2.0 / (double)n), 0.0f);
   hipLaunchKernelGGL(mse_final_kernel, dim3(1), dim3(256), 0, st, partials, nblocks, loss, (float)(1.0 / (double)n));
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_relmse(const float *pred, const float *target, int64_t n, float eps, float *loss, float *dpred,
+                  float *partials, int nblocks, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(mse_partial_kernel<true>, dim3(nblocks), dim3(256), 0, st, pred, target, n, dpred, partials,
+                     (float)(2.0 / (double)n), eps);
+  hipLaunchKernelGGL(mse_final_kernel, dim3(1), dim3(256), 0, st, partials, nblocks, loss, (float)(1.0 / (double)n));
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ------------------------------------------- Signal2SH on raw acquisitions
+__global__ void b0_inverse_mean_kernel(const float *raw, int64_t ld, const int32_t *b0idx, int nb0, int64_t V,
+                                       float *inv) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  float s = 0.0f;
+  for (int i = 0; i < nb0; ++i) s += raw[v * ld + b0idx[i]];
+  inv[v] = (float)nb0 / s;
+}
+
+int launch_b0_inverse_mean(const float *raw, int64_t ld, const int32_t *b0idx, int nb0, int64_t V, float *inv,
+                           void *stream) {
+  hipLaunchKernelGGL(b0_inverse_mean_kernel, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     raw, ld, b0idx, nb0, V, inv);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+struct ARawNorm {
+  static constexpr bool kContig = true;
+  const float *raw;
+  int64_t ld;
+  const int32_t *dwidx;
+  const float *inv;
+  int N;
+  __device__ float operator()(int64_t r, int k, int g) const { return raw[r * ld + dwidx[g * N + k]] * inv[r]; }
+  __device__ floatx4 load4(int64_t r, int k, int g) const {
+    return floatx4{(*this)(r, k, g), (*this)(r, k + 1, g), (*this)(r, k + 2, g), (*this)(r, k + 3, g)};
+  }
+};
+
+int launch_s2sh_raw(const float *raw, int64_t ld, const int32_t *dwidx, const float *inv, const float *Pf,
+                    const uint16_t *Ph, float *c, int64_t ldc, int64_t V, int S, int N, int K, dlm_precision prec,
+                    void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  ARawNorm al{raw, ld, dwidx, inv, N};
+  CRowMajor cs{c, ldc, K, 0, nullptr};
+  const Shape sh = pick_shape(K);
+  if (prec == DLM_BF16) return run_gemm_p<kOpS2shRaw, true>(al, BTableH{Ph, (int64_t)N * K, N}, cs, V, K, N, S, 0, st, sh);
+  return run_gemm_p<kOpS2shRaw, false>(al, BTableF{Pf, (int64_t)N * K, N}, cs, V, K, N, S, 0, st, sh);
 }
 
 __global__ void adam_kernel(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,

@@ -226,3 +226,27 @@ def test_lsc_empty_batch_zeroes_weight_grads():
                    outs=(None, dW, db), form=form)
         torch.cuda.synchronize()
         assert float(dW.abs().max()) == 0.0 and float(db.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_signal2sh_from_raw_fuses_b0_normalisation(prec, c2_acq):
+    acq = c2_acq
+    plan = dl.SHPlan(acq.bvecs, acq.bvals, 8, 0.006)
+    oplan = osh.SHPlan(acq.bvecs, acq.bvals, 8, 0.006)
+    b = dg.stick_ball_batch(acq, 1000 + 7, 3, 20.0, dg.rng_for(31, 2, 0))
+    raw = np.concatenate([b.raw_b0, b.x * b.raw_b0.mean(axis=1, keepdims=True)], axis=1) * 812.5
+    raw = raw.astype(np.float32).astype(np.float64)
+    c = dl.signal2sh_fwd_raw(plan, cuda(raw), precision=prec)
+    ref = osh.signal2sh(oplan, osh.normalize_b0(raw, acq.bvals, oplan))
+    assert rel(c, ref) <= TOL[prec]
+
+
+def test_relative_mse():
+    rng = np.random.default_rng(5)
+    p = rng.uniform(0.0, 1.0, 30011)
+    t = rng.uniform(0.01, 1.0, 30011)
+    loss, dp = dl.relmse_fwd_bwd(cuda(p), cuda(t), eps=1e-3)
+    l_ref, g_ref = ostack.relative_mse(p.astype(np.float32).astype(np.float64), t.astype(np.float32).astype(np.float64),
+                                       1e-3)
+    assert abs(loss.item() - l_ref) / l_ref < 1e-5
+    assert rel(dp, g_ref) < 1e-5

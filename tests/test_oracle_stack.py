@@ -126,3 +126,45 @@ def test_farthest_point_subset():
     g = dg.fibonacci_hemisphere(90)
     idx = dg.farthest_point_subset(g, 15)
     assert idx.shape == (15,) and len(set(idx.tolist())) == 15 and 0 in idx
+
+
+def test_relative_mse_definition_and_special_cases():
+    p = np.array([[1.0, 2.0], [3.0, 5.0]])
+    t = np.array([[2.0, -2.0], [3.0, 4.0]])
+    loss, g = stack.relative_mse(p, t, 0.0)
+    assert loss == pytest.approx(((1 - 2) ** 2 / 4 + (2 + 2) ** 2 / 4 + 0 + 1 / 16) / 4)
+    # constant target c: relative MSE is MSE / c^2 (eps = 0)
+    rng = np.random.default_rng(3)
+    pr = rng.standard_normal((5, 7))
+    c = 1.7
+    lr, gr = stack.relative_mse(pr, np.full_like(pr, c), 0.0)
+    lm, gm = stack.mse(pr, np.full_like(pr, c))
+    assert lr == pytest.approx(lm / c ** 2) and np.allclose(gr, gm / c ** 2)
+    # finite differences
+    tt = rng.uniform(0.2, 1.0, (4, 6))
+    eps = 1e-3
+    _, gg = stack.relative_mse(pr[:4, :6], tt, eps)
+    h = 1e-6
+    for ix in [(0, 0), (2, 3), (3, 5)]:
+        a = pr[:4, :6].copy(); a[ix] += h
+        b = pr[:4, :6].copy(); b[ix] -= h
+        fd = (stack.relative_mse(a, tt, eps)[0] - stack.relative_mse(b, tt, eps)[0]) / (2 * h)
+        assert abs(fd - gg[ix]) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_b0_normalisation_definition():
+    acq = dg.make_acquisition(7, (1000.0, 2000.0), 30, 2.0, 4)
+    plan = sh.SHPlan(acq.bvecs, acq.bvals, 4, 0.006)
+    rng = np.random.default_rng(4)
+    raw = rng.uniform(0.5, 2.0, (3, acq.bvals.size))
+    x = sh.normalize_b0(raw, acq.bvals, plan)
+    assert x.shape == (3, 60)
+    # hand check for voxel 0, first DW volume of shell 0 (acquisition index 4)
+    assert x[0, 0] == pytest.approx(raw[0, 4] / raw[0, :4].mean())
+    # scaling a voxel's raw data leaves the normalised signal unchanged
+    assert np.allclose(sh.normalize_b0(raw * 3.0, acq.bvals, plan), x)
+    # generator consistency: the datagen batches are normalised the same way
+    b = dg.stick_ball_batch(acq, 5, 2, 30.0, dg.rng_for(7, 2, 0))
+    raw_dw = b.x * b.raw_b0.mean(axis=1, keepdims=True)
+    rawfull = np.concatenate([b.raw_b0, raw_dw], axis=1)
+    assert np.allclose(sh.normalize_b0(rawfull, acq.bvals, plan), b.x)
