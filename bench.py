@@ -37,6 +37,9 @@ MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=["c2", "c4"], default="c2",
+                    help="c2: three-shell stack fwd+bwd over 2^20 voxels (the headline); "
+                         "c4: four-layer training step (fwd, MSE, bwd, Adam) on 8192-voxel batches")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32")
@@ -128,8 +131,72 @@ def cpu_baseline(w, acq, target_s):
                       f"1024-voxel chunks, {dt:.1f} s"}
 
 
+def bench_c4(args):
+    """Training steps of the four-layer network; each batch has its own
+    distorted gradient table (plan tables rebuilt in float64 and uploaded on
+    the stream) and its own voxels; layers 1 and 3 recompute their outputs."""
+    import torch
+
+    import datagen as dg
+    from paper_1808_01517_amd import apps
+
+    dev = torch.device("cuda:0")
+    prec, form = args.precision, args.form
+    w = dg.C4
+    B = w.voxels
+    net, acq = apps.c4_network(prec, form, recompute=(0, 2), batch=B)
+    nb = 8
+    batches = []
+    for i in range(nb):
+        dacq, x, clean = apps.c4_batch(acq, i, B)
+        batches.append((dacq.bvecs, torch.from_numpy(x).to(dev), torch.from_numpy(clean).to(dev)))
+
+    def step(i):
+        bvecs, x, clean = batches[i % nb]
+        net.plan_in.update_gradients(bvecs)
+        net.train_step(x, clean, lr=1e-4)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for i in range(args.steps):
+        step(args.warmup + i)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    result = {"metric": "voxels/s training step (fwd + MSE + bwd + Adam), 4-layer LSC 3-32-64-32-3, 3x90 dirs, L=8",
+              "value": round(B / (ms / 1e3), 1), "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
+              "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+              "vs_baseline": None, "dtype": "f32" if prec == "fp32" else "bf16", "data": "synthetic",
+              "config": {"workload": w.name, "batch": B, "lsc_channels": list(w.channels), "sh_order": w.sh_order,
+                         "distortion_deg": 3.0, "recompute_layers": [1, 3], "lsc_form": form, "precision": prec}}
+    if not args.no_kernel_timing:
+        import paper_1808_01517_amd as dl
+        dl.timing_reset()
+        dl.timing_enable(True)
+        for i in range(args.steps):
+            step(i)
+        torch.cuda.synchronize()
+        dl.timing_enable(False)
+        rep = dl.timing_report()
+        top = max(rep.items(), key=lambda kv: kv[1][0])
+        result["roofline"] = roofline(top[0], *top[1], prec)
+        result["kernels"] = {t: {"ms_per_step": round(v[0] / args.steps, 4), "launches_per_step": v[1] // args.steps}
+                             for t, v in sorted(rep.items(), key=lambda kv: -kv[1][0])}
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "c4":
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        bench_c4(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the layers are per-voxel and this build "
               "measures a single GPU's share; see the sharding notes in the design document.", file=sys.stderr)

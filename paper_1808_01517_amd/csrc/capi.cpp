@@ -630,7 +630,7 @@ struct FoldWs {
   uint16_t *Twh = nullptr, *TwTh = nullptr;
 };
 
-constexpr int kFoldSplitMax = 64;
+constexpr int kFoldSplitMax = 128;
 
 size_t fold_ws_need(const dlm_lsc_plan *p, int C, int O) {
   const size_t M = size_t(O) * p->K_out, CK = size_t(C) * p->K_in, N1 = CK + 1;

@@ -52,18 +52,29 @@ constexpr int lds_stride(int B) {
   return (B % 64 == 16 || B % 64 == 48) ? B : B + ((B % 64) < 16 ? 16 - B % 64 : (B % 64) < 48 ? 48 - B % 64 : 80 - B % 64);
 }
 
-// Block index -> (M tile, N tile).  Workgroups are dispatched round-robin
-// over the 8 XCDs; consecutive logical tiles are gathered onto one XCD so
-// the N tiles that share an A row-block run together and hit the same L2.
+// Block index -> (group / split z, M tile, N tile).  The grid is 1-D over
+// nbM * nbN * Z blocks, dispatched round-robin over the 8 XCDs; the block
+// index is remapped so that consecutive logical tiles land on one XCD and
+// share its L2.  Logical order: split-K (ZOUTER) puts all tiles of one voxel
+// slice together (they stream the same activation rows); grouped GEMMs put
+// the groups of one row-block together, then their N tiles.
 struct TileMap {
-  int mt, nt;
-  __device__ TileMap(int b, int nbM, int nbN) {
-    const int total = nbM * nbN;
+  int mt, nt, z;
+  __device__ TileMap(int b, int nbM, int nbN, int Z, bool zouter) {
+    const int total = nbM * nbN * Z;
     const int q = total >> 3, r = total & 7;
     const int xcd = b & 7, local = b >> 3;
     const int L = xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
-    mt = L / nbN;
-    nt = L - mt * nbN;
+    if (zouter) {
+      z = L / (nbM * nbN);
+      const int t = L - z * nbM * nbN;
+      mt = t / nbN;
+      nt = t - mt * nbN;
+    } else {
+      nt = L % nbN;
+      z = (L / nbN) % Z;
+      mt = L / (nbN * Z);
+    }
   }
 };
 
@@ -96,7 +107,7 @@ struct Runs {
 // the reduction index applied identically to A and B.
 template <int OP, class CF, class AL, class BL, class CS>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(AL al, BL bl, CS cs, int64_t M, int N, int K, int ksplit,
-                                                       int nbM, int nbN) {
+                                                       int nbM, int nbN, int nz) {
   constexpr int BM = CF::BM, BN = CF::BN, BK = 16;
   constexpr bool AK = AL::kContig, BKC = BL::kContig;
   constexpr int SA = AK ? BK + 4 : lds_stride(BM);
@@ -110,10 +121,10 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(AL al, BL bl, CS cs, int6
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % CF::WM, wn = wave / CF::WM;
   const int q16 = lane & 15, g4 = lane >> 4;
-  const TileMap tm(blockIdx.x, nbM, nbN);
+  const TileMap tm(blockIdx.x, nbM, nbN, nz, ksplit > 0);
   const int64_t m0 = (int64_t)tm.mt * BM;
   const int n0 = tm.nt * BN;
-  const int g = blockIdx.z;
+  const int g = tm.z;
   int kbeg = 0, kend = K;
   if (ksplit > 0) {
     kbeg = g * ksplit;
@@ -240,65 +251,78 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(AL al, BL bl, CS cs, int6
       for (int i = 0; i < CF::TM; ++i)
 #pragma unroll
         for (int jn = 0; jn < CF::TN; ++jn)
-          acc[i][jn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][j], b[jn][j], acc[i][jn], 0, 0, 0);
+          acc[i][jn] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[jn][j], a[i][j], acc[i][jn], 0, 0, 0);
     if (it + 1 < niter) stash(cur ^ 1);
     __syncthreads();
   }
+  // The MFMAs take the B fragment as their first operand, so each 16 x 16
+  // accumulator is the transposed tile: lane l holds row m = l % 16 and the
+  // four consecutive columns 4 (l / 16) .. +3, stored as one 16-byte run.
 #pragma unroll
-  for (int i = 0; i < CF::TM; ++i)
+  for (int i = 0; i < CF::TM; ++i) {
+    const int64_t r = m0 + (wm * CF::TM + i) * 16 + q16;
+    if (r >= M) continue;
 #pragma unroll
-    for (int j = 0; j < CF::TN; ++j)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t r = m0 + (wm * CF::TM + i) * 16 + 4 * g4 + q;
-        const int n = n0 + (wn * CF::TN + j) * 16 + q16;
-        if (r < M && n < N) cs(r, n, g, acc[i][j][q]);
+    for (int j = 0; j < CF::TN; ++j) {
+      const int n = n0 + (wn * CF::TN + j) * 16 + 4 * g4;
+      if (n + 3 < N) {
+        cs.store4(r, n, g, acc[i][j]);
+      } else {
+        for (int q = 0; q < 4; ++q)
+          if (n + q < N) cs(r, n + q, g, acc[i][j][q]);
       }
+    }
+  }
 }
 
 // ------------------------------------------------------------- BF16 core
 // LDS holds both operands row-major with BK bfloat16 per row (k
 // contiguous, row stride BK+8) so each lane reads its 8 consecutive k with
-// one 128-bit load.  k-contiguous operands arrive as runs of 4 k (one
-// 64-bit LDS store after conversion); row-contiguous operands arrive as 4
-// rows x 2 consecutive k (four 32-bit stores of bf16 pairs).
+// one 128-bit load.  The 16-byte chunk c of row r is stored at chunk
+// c ^ ((r >> 4) & 3), which keeps both the staging stores and the MFMA
+// reads free of bank conflicts.  k-contiguous operands arrive as runs of
+// 4 k (one 64-bit store after conversion); row-contiguous operands arrive
+// as 4 rows x 8 k per lane (eight 16-byte loads, each coalesced across the
+// neighbouring rows of neighbouring lanes, then four 128-bit stores).
 __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
   return (uint32_t)to_bf16_bits(lo) | ((uint32_t)to_bf16_bits(hi) << 16);
 }
 
 template <int OP, class CF, class AL, class BL, class CS>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int64_t M, int N, int K, int ksplit,
-                                                        int nbM, int nbN) {
+                                                        int nbM, int nbN, int nz) {
   constexpr int BM = CF::BM, BN = CF::BN, BK = 32, LD = BK + 8;
   constexpr bool AK = AL::kContig, BKC = BL::kContig;
   constexpr bool BT = std::is_same<typename BL::type, uint16_t>::value;
   static_assert(!BT || BKC, "bfloat16 tables are k-contiguous");
-  // items per tile: k-contiguous -> runs of 4 k; row-contiguous -> 4 rows x 2 k
-  constexpr int NA = AK ? BM * BK / 4 : (BM / 4) * (BK / 2);
-  constexpr int NB = BKC ? BN * BK / 4 : (BN / 4) * (BK / 2);
+  // items per tile: k-contiguous -> runs of 4 k; row-contiguous -> 4 rows x 8 k
+  constexpr int NA = AK ? BM * BK / 4 : (BM / 4) * (BK / 8);
+  constexpr int NB = BKC ? BN * BK / 4 : (BN / 4) * (BK / 8);
   constexpr int PA = (NA + 255) / 256, PB = (NB + 255) / 256;
   __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LD];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % CF::WM, wn = wave / CF::WM;
   const int q16 = lane & 15, g4 = lane >> 4;
-  const TileMap tm(blockIdx.x, nbM, nbN);
+  const TileMap tm(blockIdx.x, nbM, nbN, nz, ksplit > 0);
   const int64_t m0 = (int64_t)tm.mt * BM;
   const int n0 = tm.nt * BN;
-  const int g = blockIdx.z;
+  const int g = tm.z;
   int kbeg = 0, kend = K;
   if (ksplit > 0) {
     kbeg = g * ksplit;
     kend = min(K, kbeg + ksplit);
   }
-  // register staging: k-contiguous items need 2 words, row-contiguous 4
-  uint32_t ra[PA][AK ? 2 : 4], rb[PB][BKC ? 2 : 4];
+  // register staging: k-contiguous items need 2 words, row-contiguous 16
+  uint32_t ra[PA][AK ? 2 : 16], rb[PB][BKC ? 2 : 16];
   auto coordA = [&](int e, int &row, int &kk) {
-    if constexpr (AK) { kk = 4 * (e % (BK / 4)); row = e / (BK / 4); } else { row = 4 * (e % (BM / 4)); kk = 2 * (e / (BM / 4)); }
+    if constexpr (AK) { kk = 4 * (e % (BK / 4)); row = e / (BK / 4); } else { row = 4 * (e % (BM / 4)); kk = 8 * (e / (BM / 4)); }
   };
   auto coordB = [&](int e, int &col, int &kk) {
-    if constexpr (BKC) { kk = 4 * (e % (BK / 4)); col = e / (BK / 4); } else { col = 4 * (e % (BN / 4)); kk = 2 * (e / (BN / 4)); }
+    if constexpr (BKC) { kk = 4 * (e % (BK / 4)); col = e / (BK / 4); } else { col = 4 * (e % (BN / 4)); kk = 8 * (e / (BN / 4)); }
   };
+  // LDS element offset of (row, k) under the chunk swizzle
+  auto sw = [&](int row, int k) { return row * LD + 8 * ((k >> 3) ^ ((row >> 4) & 3)) + (k & 7); };
   auto load = [&](int k0) {
 #pragma unroll
     for (int p = 0; p < PA; ++p) {
@@ -317,18 +341,18 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
         ra[p][0] = pack_bf16(v[0], v[1]);
         ra[p][1] = pack_bf16(v[2], v[3]);
       } else {
-        floatx4 v0 = {0.f, 0.f, 0.f, 0.f}, v1 = {0.f, 0.f, 0.f, 0.f};
-        if (r + 3 < M) {
-          if (k < kend) v0 = al.load4(r, k, g);
-          if (k + 1 < kend) v1 = al.load4(r, k + 1, g);
-        } else {
-          for (int i = 0; i < 4; ++i)
-            if (r + i < M) {
-              if (k < kend) v0[i] = al(r + i, k, g);
-              if (k + 1 < kend) v1[i] = al(r + i, k + 1, g);
-            }
+        floatx4 v[8];
+        for (int j = 0; j < 8; ++j) {
+          v[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+          if (k + j < kend) {
+            if (r + 3 < M) v[j] = al.load4(r, k + j, g);
+            else
+              for (int i = 0; i < 4; ++i)
+                if (r + i < M) v[j][i] = al(r + i, k + j, g);
+          }
         }
-        for (int i = 0; i < 4; ++i) ra[p][i] = pack_bf16(v0[i], v1[i]);
+        for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j) ra[p][4 * i + j] = pack_bf16(v[2 * j][i], v[2 * j + 1][i]);
       }
     }
 #pragma unroll
@@ -363,18 +387,18 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
         rb[p][0] = pack_bf16(v[0], v[1]);
         rb[p][1] = pack_bf16(v[2], v[3]);
       } else {
-        floatx4 v0 = {0.f, 0.f, 0.f, 0.f}, v1 = {0.f, 0.f, 0.f, 0.f};
-        if (n + 3 < N) {
-          if (k < kend) v0 = bl.load4(n, k, g);
-          if (k + 1 < kend) v1 = bl.load4(n, k + 1, g);
-        } else {
-          for (int i = 0; i < 4; ++i)
-            if (n + i < N) {
-              if (k < kend) v0[i] = bl(n + i, k, g);
-              if (k + 1 < kend) v1[i] = bl(n + i, k + 1, g);
-            }
+        floatx4 v[8];
+        for (int j = 0; j < 8; ++j) {
+          v[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+          if (k + j < kend) {
+            if (n + 3 < N) v[j] = bl.load4(n, k + j, g);
+            else
+              for (int i = 0; i < 4; ++i)
+                if (n + i < N) v[j][i] = bl(n + i, k + j, g);
+          }
         }
-        for (int i = 0; i < 4; ++i) rb[p][i] = pack_bf16(v0[i], v1[i]);
+        for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j) rb[p][4 * i + j] = pack_bf16(v[2 * j][i], v[2 * j + 1][i]);
       }
     }
   };
@@ -386,9 +410,11 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
       int row, kk;
       coordA(e, row, kk);
       if constexpr (AK) {
-        *reinterpret_cast<uint2 *>(&As[buf][row * LD + kk]) = make_uint2(ra[p][0], ra[p][1]);
+        *reinterpret_cast<uint2 *>(&As[buf][sw(row, kk)]) = make_uint2(ra[p][0], ra[p][1]);
       } else {
-        for (int i = 0; i < 4; ++i) *reinterpret_cast<uint32_t *>(&As[buf][(row + i) * LD + kk]) = ra[p][i];
+        for (int i = 0; i < 4; ++i)
+          *reinterpret_cast<uint4 *>(&As[buf][sw(row + i, kk)]) =
+              make_uint4(ra[p][4 * i], ra[p][4 * i + 1], ra[p][4 * i + 2], ra[p][4 * i + 3]);
       }
     }
 #pragma unroll
@@ -398,9 +424,11 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
       int col, kk;
       coordB(e, col, kk);
       if constexpr (BKC) {
-        *reinterpret_cast<uint2 *>(&Bs[buf][col * LD + kk]) = make_uint2(rb[p][0], rb[p][1]);
+        *reinterpret_cast<uint2 *>(&Bs[buf][sw(col, kk)]) = make_uint2(rb[p][0], rb[p][1]);
       } else {
-        for (int i = 0; i < 4; ++i) *reinterpret_cast<uint32_t *>(&Bs[buf][(col + i) * LD + kk]) = rb[p][i];
+        for (int i = 0; i < 4; ++i)
+          *reinterpret_cast<uint4 *>(&Bs[buf][sw(col + i, kk)]) =
+              make_uint4(rb[p][4 * i], rb[p][4 * i + 1], rb[p][4 * i + 2], rb[p][4 * i + 3]);
       }
     }
   };
@@ -422,27 +450,35 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
     bf16x8 a[CF::TM], b[CF::TN];
 #pragma unroll
     for (int i = 0; i < CF::TM; ++i)
-      a[i] = *reinterpret_cast<const bf16x8 *>(&As[cur][((wm * CF::TM + i) * 16 + q16) * LD + 8 * g4]);
+      a[i] = *reinterpret_cast<const bf16x8 *>(&As[cur][sw((wm * CF::TM + i) * 16 + q16, 8 * g4)]);
 #pragma unroll
     for (int j = 0; j < CF::TN; ++j)
-      b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[cur][((wn * CF::TN + j) * 16 + q16) * LD + 8 * g4]);
+      b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[cur][sw((wn * CF::TN + j) * 16 + q16, 8 * g4)]);
 #pragma unroll
     for (int i = 0; i < CF::TM; ++i)
 #pragma unroll
-      for (int j = 0; j < CF::TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+      for (int j = 0; j < CF::TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j], a[i], acc[i][j], 0, 0, 0);
     if (it + 1 < niter) stash(cur ^ 1);
     __syncthreads();
   }
+  // The MFMAs take the B fragment as their first operand, so each 16 x 16
+  // accumulator is the transposed tile: lane l holds row m = l % 16 and the
+  // four consecutive columns 4 (l / 16) .. +3, stored as one 16-byte run.
 #pragma unroll
-  for (int i = 0; i < CF::TM; ++i)
+  for (int i = 0; i < CF::TM; ++i) {
+    const int64_t r = m0 + (wm * CF::TM + i) * 16 + q16;
+    if (r >= M) continue;
 #pragma unroll
-    for (int j = 0; j < CF::TN; ++j)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t r = m0 + (wm * CF::TM + i) * 16 + 4 * g4 + q;
-        const int n = n0 + (wn * CF::TN + j) * 16 + q16;
-        if (r < M && n < N) cs(r, n, g, acc[i][j][q]);
+    for (int j = 0; j < CF::TN; ++j) {
+      const int n = n0 + (wn * CF::TN + j) * 16 + 4 * g4;
+      if (n + 3 < N) {
+        cs.store4(r, n, g, acc[i][j]);
+      } else {
+        for (int q = 0; q < 4; ++q)
+          if (n + q < N) cs(r, n + q, g, acc[i][j][q]);
       }
+    }
+  }
 }
 
 // ------------------------------------------------------------- launching
@@ -464,14 +500,14 @@ static int run_gemm_p(AL al, BL bl, CS cs, int64_t M, int N, int K, int Z, int k
   do {                                                                                                           \
     const int64_t nbM = (M + CFG::BM - 1) / CFG::BM;                                                             \
     const int nbN = (N + CFG::BN - 1) / CFG::BN;                                                                 \
-    if (nbM * nbN > 0x7fffffff) return -4;                                                                       \
-    dim3 grid((unsigned)(nbM * nbN), 1, (unsigned)Z);                                                            \
+    if (nbM * nbN * Z > 0x7fffffff) return -4;                                                                   \
+    dim3 grid((unsigned)(nbM * nbN * Z));                                                                        \
     if constexpr (BF16)                                                                                          \
       hipLaunchKernelGGL((gemm_bf16_kernel<OP, CFG, AL, BL, CS>), grid, dim3(256), 0, st, al, bl, cs, M, N, K,    \
-                         ksplit, (int)nbM, nbN);                                                                 \
+                         ksplit, (int)nbM, nbN, Z);                                                              \
     else                                                                                                         \
       hipLaunchKernelGGL((gemm_f32_kernel<OP, CFG, AL, BL, CS>), grid, dim3(256), 0, st, al, bl, cs, M, N, K,     \
-                         ksplit, (int)nbM, nbN);                                                                 \
+                         ksplit, (int)nbM, nbN, Z);                                                              \
   } while (0)
   switch (shape) {
     case Shape::S96: DLM_LAUNCH(Cfg96); break;
@@ -546,6 +582,15 @@ struct CRowMajor {
     if (bias_n) v += bias_n[n];
     if (relu) v = fmaxf(v, 0.0f);
     C[r * ldc + (int64_t)g * gs + n] = v;
+  }
+  __device__ void store4(int64_t r, int n, int g, floatx4 v) const {
+    if (bias_n) {
+      const floatx4 b = ld4(bias_n + n);
+      for (int q = 0; q < 4; ++q) v[q] += b[q];
+    }
+    if (relu)
+      for (int q = 0; q < 4; ++q) v[q] = fmaxf(v[q], 0.0f);
+    __builtin_memcpy(C + r * ldc + (int64_t)g * gs + n, &v, 16);
   }
 };
 
@@ -625,6 +670,9 @@ struct CSignalY {
     if (bias) v += bias[o];
     y[(vx * O + o) * m + i] = v;
   }
+  __device__ void store4(int64_t r, int n, int g, floatx4 v) const {
+    for (int q = 0; q < 4; ++q) (*this)(r, n + q, g, v[q]);
+  }
 };
 
 int launch_lsc_contract_fwd(const float *X, const float *W, const uint16_t *Wh, const float *bias, float *y,
@@ -664,6 +712,9 @@ struct CNbhd {
     const int c = n / T, t = n - c * T;
     const int64_t P = (int64_t)m * T;
     dX[(v * C + c) * P + (int64_t)i * T + t] = val;
+  }
+  __device__ void store4(int64_t r, int n, int g, floatx4 v) const {
+    for (int q = 0; q < 4; ++q) (*this)(r, n + q, g, v[q]);
   }
 };
 
@@ -717,6 +768,9 @@ struct CPartial {
   int rows, O;
   __device__ void operator()(int64_t r, int o, int s, float v) const {
     part[((int64_t)s * rows + r) * O + o] = v;
+  }
+  __device__ void store4(int64_t r, int n, int g, floatx4 v) const {
+    for (int q = 0; q < 4; ++q) (*this)(r, n + q, g, v[q]);
   }
 };
 
@@ -773,6 +827,9 @@ struct CFold {
     TwT[b] = v;
     if (Twh) Twh[a] = to_bf16_bits(v);
     if (TwTh) TwTh[b] = to_bf16_bits(v);
+  }
+  __device__ void store4(int64_t r, int n, int g, floatx4 v) const {
+    for (int q = 0; q < 4; ++q) (*this)(r, n + q, g, v[q]);
   }
 };
 
@@ -878,6 +935,13 @@ struct CPartial2 {
     else
       part[((int64_t)s * M + r) * N1 + c] = v;
   }
+  __device__ void store4(int64_t r, int c, int s, floatx4 v) const {
+    if constexpr (TRANS) {
+      for (int q = 0; q < 4; ++q) part[((int64_t)s * M + c + q) * N1 + r] = v[q];
+    } else {
+      __builtin_memcpy(part + ((int64_t)s * M + r) * N1 + c, &v, 16);
+    }
+  }
 };
 
 static int split_len(int64_t K, int splits) {
@@ -886,9 +950,16 @@ static int split_len(int64_t K, int splits) {
   return (ks + bk - 1) / bk * bk;
 }
 
+static Shape grad_shape(int M, int N1) {
+  // the smaller side (135/136 for the three-shell layers) fits one 144-wide
+  // tile, so the larger operand is read once; otherwise 64 x 64
+  return std::min(M, N1) <= 144 ? Shape::S144 : Shape::S64;
+}
+
 int fold_grad_splits(int64_t V, int M, int N1) {
-  const int64_t tiles = ((std::max(M, N1) + 63) / 64) * ((std::min(M, N1) + 63) / 64);
-  int s = (int)std::min<int64_t>(64, std::max<int64_t>(1, (4096 + tiles - 1) / tiles));
+  const int big = std::max(M, N1), small = std::min(M, N1);
+  const int64_t tiles = grad_shape(M, N1) == Shape::S144 ? (big + 127) / 128 : ((big + 63) / 64) * ((small + 63) / 64);
+  int s = (int)std::min<int64_t>(128, std::max<int64_t>(1, (2048 + tiles - 1) / tiles));
   s = (int)std::min<int64_t>(s, std::max<int64_t>(1, V / 512));
   while (s > 1 && (V + split_len(V, s) - 1) / split_len(V, s) != s) --s;
   return s;
@@ -900,11 +971,12 @@ int launch_lsc_fold_grad(const float *da_out, const float *mask, const float *a_
   const int ks = split_len(V, splits);
   if ((V + ks - 1) / ks != splits) return -2;
   hipStream_t st = (hipStream_t)stream;
+  const Shape sh = grad_shape(M, N1);
   if (M >= N1)
     return run_gemm<kOpFoldGrad>(AGradT{da_out, mask, M}, BActT{a_in, CK}, CPartial2<false>{partial, M, N1}, M, N1,
-                                 (int)V, splits, ks, prec, st, Shape::S64);
+                                 (int)V, splits, ks, prec, st, sh);
   return run_gemm<kOpFoldGrad>(AActT{a_in, CK}, BGradT{da_out, mask, M}, CPartial2<true>{partial, M, N1}, N1, M,
-                               (int)V, splits, ks, prec, st, Shape::S64);
+                               (int)V, splits, ks, prec, st, sh);
 }
 
 __global__ void sum_partials_kernel(const float *part, int splits, int64_t n, float *out) {
