@@ -87,7 +87,11 @@ __device__ __forceinline__ floatx4 ld4(const float *p) {
 // Operand staging.  An operand is "k-contiguous" (kContig) or contiguous
 // along its row index.  Threads move runs of 4 elements along the
 // contiguous dimension: op.load4(row, k, g) for a run that lies inside the
-// matrix, element-wise op(row, k, g) with zero fill at ragged edges.
+// matrix, element-wise op(row, k, g) with zero fill at ragged edges.  The
+// load phase only issues loads into registers; masking (op.kMask: element
+// kept where op.mask4 / op.maskv > 0) and any conversion happen when the
+// registers are written to LDS, after the current slice's MFMAs, so the
+// prefetch latency overlaps the math.
 template <class OPND, int ROWS, int BK>
 struct Runs {
   static constexpr bool KC = OPND::kContig;
@@ -95,6 +99,30 @@ struct Runs {
   static constexpr int PER = (NRUN + 255) / 256;            // runs per thread
   __device__ static void coord(int e, int &row, int &k) {
     if constexpr (KC) { k = 4 * (e % (BK / 4)); row = e / (BK / 4); } else { row = 4 * (e % (ROWS / 4)); k = e / (ROWS / 4); }
+  }
+  // raw values (and mask values when the operand has one) of run (r, k)
+  __device__ static void fetch(const OPND &op, int64_t r, int k, int64_t rows, int kend, int g, floatx4 &v, floatx4 &m) {
+    const bool full = KC ? (r < rows && k + 3 < kend) : (r + 3 < rows && k < kend);
+    if (full) {
+      v = op.load4(r, k, g);
+      if constexpr (OPND::kMask) m = op.mask4(r, k, g);
+    } else {
+      v = floatx4{0.f, 0.f, 0.f, 0.f};
+      m = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int i = 0; i < 4; ++i) {
+        const int64_t ri = KC ? r : r + i;
+        const int ki = KC ? k + i : k;
+        if (ri < rows && ki < kend) {
+          v[i] = op(ri, ki, g);
+          if constexpr (OPND::kMask) m[i] = op.maskv(ri, ki, g);
+        }
+      }
+    }
+  }
+  __device__ static floatx4 finish(floatx4 v, floatx4 m) {
+    if constexpr (OPND::kMask)
+      for (int i = 0; i < 4; ++i) v[i] = m[i] > 0.0f ? v[i] : 0.0f;
+    return v;
   }
 };
 
@@ -130,65 +158,21 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(AL al, BL bl, CS cs, int6
     kbeg = g * ksplit;
     kend = min(K, kbeg + ksplit);
   }
-  floatx4 ra[RA::PER], rb[RB::PER];
+  floatx4 ra[RA::PER], rb[RB::PER], ma[RA::PER], mb[RB::PER];
   auto load = [&](int k0) {
 #pragma unroll
     for (int p = 0; p < RA::PER; ++p) {
       const int e = tid + p * 256;
       int row, kk;
       RA::coord(e, row, kk);
-      if (e < RA::NRUN) {
-        const int64_t r = m0 + row;
-        const int k = k0 + kk;
-        if constexpr (AK) {
-          if (r < M && k + 3 < kend) ra[p] = al.load4(r, k, g);
-          else {
-            floatx4 v = {0.f, 0.f, 0.f, 0.f};
-            if (r < M)
-              for (int i = 0; i < 4; ++i)
-                if (k + i < kend) v[i] = al(r, k + i, g);
-            ra[p] = v;
-          }
-        } else {
-          if (r + 3 < M && k < kend) ra[p] = al.load4(r, k, g);
-          else {
-            floatx4 v = {0.f, 0.f, 0.f, 0.f};
-            if (k < kend)
-              for (int i = 0; i < 4; ++i)
-                if (r + i < M) v[i] = al(r + i, k, g);
-            ra[p] = v;
-          }
-        }
-      }
+      if (e < RA::NRUN) RA::fetch(al, m0 + row, k0 + kk, M, kend, g, ra[p], ma[p]);
     }
 #pragma unroll
     for (int p = 0; p < RB::PER; ++p) {
       const int e = tid + p * 256;
       int col, kk;
       RB::coord(e, col, kk);
-      if (e < RB::NRUN) {
-        const int n = n0 + col;
-        const int k = k0 + kk;
-        if constexpr (BKC) {
-          if (n < N && k + 3 < kend) rb[p] = bl.load4(n, k, g);
-          else {
-            floatx4 v = {0.f, 0.f, 0.f, 0.f};
-            if (n < N)
-              for (int i = 0; i < 4; ++i)
-                if (k + i < kend) v[i] = bl(n, k + i, g);
-            rb[p] = v;
-          }
-        } else {
-          if (n + 3 < N && k < kend) rb[p] = bl.load4(n, k, g);
-          else {
-            floatx4 v = {0.f, 0.f, 0.f, 0.f};
-            if (k < kend)
-              for (int i = 0; i < 4; ++i)
-                if (n + i < N) v[i] = bl(n + i, k, g);
-            rb[p] = v;
-          }
-        }
-      }
+      if (e < RB::NRUN) RB::fetch(bl, n0 + col, k0 + kk, N, kend, g, rb[p], mb[p]);
     }
   };
   auto stash = [&](int buf) {
@@ -198,8 +182,9 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(AL al, BL bl, CS cs, int6
       int row, kk;
       RA::coord(e, row, kk);
       if (e < RA::NRUN) {
-        if constexpr (AK) *reinterpret_cast<floatx4 *>(&As[buf][row * SA + kk]) = ra[p];
-        else *reinterpret_cast<floatx4 *>(&As[buf][kk * SA + row]) = ra[p];
+        const floatx4 v = RA::finish(ra[p], ma[p]);
+        if constexpr (AK) *reinterpret_cast<floatx4 *>(&As[buf][row * SA + kk]) = v;
+        else *reinterpret_cast<floatx4 *>(&As[buf][kk * SA + row]) = v;
       }
     }
 #pragma unroll
@@ -208,8 +193,9 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(AL al, BL bl, CS cs, int6
       int col, kk;
       RB::coord(e, col, kk);
       if (e < RB::NRUN) {
-        if constexpr (BKC) *reinterpret_cast<floatx4 *>(&Bs[buf][col * SB + kk]) = rb[p];
-        else *reinterpret_cast<floatx4 *>(&Bs[buf][kk * SB + col]) = rb[p];
+        const floatx4 v = RB::finish(rb[p], mb[p]);
+        if constexpr (BKC) *reinterpret_cast<floatx4 *>(&Bs[buf][col * SB + kk]) = v;
+        else *reinterpret_cast<floatx4 *>(&Bs[buf][kk * SB + col]) = v;
       }
     }
   };
@@ -280,10 +266,10 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(AL al, BL bl, CS cs, int6
 // contiguous, row stride BK+8) so each lane reads its 8 consecutive k with
 // one 128-bit load.  The 16-byte chunk c of row r is stored at chunk
 // c ^ ((r >> 4) & 3), which keeps both the staging stores and the MFMA
-// reads free of bank conflicts.  k-contiguous operands arrive as runs of
-// 4 k (one 64-bit store after conversion); row-contiguous operands arrive
-// as 4 rows x 8 k per lane (eight 16-byte loads, each coalesced across the
-// neighbouring rows of neighbouring lanes, then four 128-bit stores).
+// reads free of bank conflicts.  Every operand moves as 16-byte runs of 4
+// floats (k-contiguous: 4 k of one row; row-contiguous: 4 rows of one k);
+// conversion to bfloat16 (round to nearest even) happens when a run is
+// written to LDS.  bfloat16 tables arrive as 8-byte runs of 4 k.
 __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
   return (uint32_t)to_bf16_bits(lo) | ((uint32_t)to_bf16_bits(hi) << 16);
 }
@@ -295,10 +281,13 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
   constexpr bool AK = AL::kContig, BKC = BL::kContig;
   constexpr bool BT = std::is_same<typename BL::type, uint16_t>::value;
   static_assert(!BT || BKC, "bfloat16 tables are k-contiguous");
-  // items per tile: k-contiguous -> runs of 4 k; row-contiguous -> 4 rows x 8 k
-  constexpr int NA = AK ? BM * BK / 4 : (BM / 4) * (BK / 8);
-  constexpr int NB = BKC ? BN * BK / 4 : (BN / 4) * (BK / 8);
+  using RA = Runs<AL, BM, BK>;
+  using RB = Runs<BL, BN, BK>;
+  // row-contiguous runs are grouped in 4 consecutive k (4 rows x 4 k per item)
+  constexpr int NA = AK ? RA::NRUN : RA::NRUN / 4;
+  constexpr int NB = BKC ? RB::NRUN : RB::NRUN / 4;
   constexpr int PA = (NA + 255) / 256, PB = (NB + 255) / 256;
+  constexpr int QA = AK ? 1 : 4, QB = BKC ? 1 : 4;
   __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LD];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -313,15 +302,14 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
     kbeg = g * ksplit;
     kend = min(K, kbeg + ksplit);
   }
-  // register staging: k-contiguous items need 2 words, row-contiguous 16
-  uint32_t ra[PA][AK ? 2 : 16], rb[PB][BKC ? 2 : 16];
+  floatx4 ra[PA][QA], ma[PA][QA], rb[PB][QB], mb[PB][QB];
+  uint2 rt[BT ? PB : 1];
   auto coordA = [&](int e, int &row, int &kk) {
-    if constexpr (AK) { kk = 4 * (e % (BK / 4)); row = e / (BK / 4); } else { row = 4 * (e % (BM / 4)); kk = 8 * (e / (BM / 4)); }
+    if constexpr (AK) { kk = 4 * (e % (BK / 4)); row = e / (BK / 4); } else { row = 4 * (e % (BM / 4)); kk = 4 * (e / (BM / 4)); }
   };
   auto coordB = [&](int e, int &col, int &kk) {
-    if constexpr (BKC) { kk = 4 * (e % (BK / 4)); col = e / (BK / 4); } else { col = 4 * (e % (BN / 4)); kk = 8 * (e / (BN / 4)); }
+    if constexpr (BKC) { kk = 4 * (e % (BK / 4)); col = e / (BK / 4); } else { col = 4 * (e % (BN / 4)); kk = 4 * (e / (BN / 4)); }
   };
-  // LDS element offset of (row, k) under the chunk swizzle
   auto sw = [&](int row, int k) { return row * LD + 8 * ((k >> 3) ^ ((row >> 4) & 3)) + (k & 7); };
   auto load = [&](int k0) {
 #pragma unroll
@@ -330,30 +318,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
       if (e >= NA) continue;
       int row, kk;
       coordA(e, row, kk);
-      const int64_t r = m0 + row;
-      const int k = k0 + kk;
-      if constexpr (AK) {
-        floatx4 v = {0.f, 0.f, 0.f, 0.f};
-        if (r < M && k + 3 < kend) v = al.load4(r, k, g);
-        else if (r < M)
-          for (int i = 0; i < 4; ++i)
-            if (k + i < kend) v[i] = al(r, k + i, g);
-        ra[p][0] = pack_bf16(v[0], v[1]);
-        ra[p][1] = pack_bf16(v[2], v[3]);
-      } else {
-        floatx4 v[8];
-        for (int j = 0; j < 8; ++j) {
-          v[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-          if (k + j < kend) {
-            if (r + 3 < M) v[j] = al.load4(r, k + j, g);
-            else
-              for (int i = 0; i < 4; ++i)
-                if (r + i < M) v[j][i] = al(r + i, k + j, g);
-          }
-        }
-        for (int i = 0; i < 4; ++i)
-          for (int j = 0; j < 4; ++j) ra[p][4 * i + j] = pack_bf16(v[2 * j][i], v[2 * j + 1][i]);
-      }
+      for (int q = 0; q < QA; ++q) RA::fetch(al, m0 + row, k0 + kk + q, M, kend, g, ra[p][q], ma[p][q]);
     }
 #pragma unroll
     for (int p = 0; p < PB; ++p) {
@@ -364,41 +329,17 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
       const int n = n0 + col;
       const int k = k0 + kk;
       if constexpr (BT) {
-        uint32_t w0 = 0u, w1 = 0u;
         if (n < N && k + 3 < kend) {
-          const uint2 h = bl.load4h(n, k, g);
-          w0 = h.x;
-          w1 = h.y;
-        } else if (n < N) {
+          rt[p] = bl.load4h(n, k, g);
+        } else {
           uint32_t h[4] = {0u, 0u, 0u, 0u};
-          for (int i = 0; i < 4; ++i)
-            if (k + i < kend) h[i] = bl(n, k + i, g);
-          w0 = h[0] | (h[1] << 16);
-          w1 = h[2] | (h[3] << 16);
+          if (n < N)
+            for (int i = 0; i < 4; ++i)
+              if (k + i < kend) h[i] = bl(n, k + i, g);
+          rt[p] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
         }
-        rb[p][0] = w0;
-        rb[p][1] = w1;
-      } else if constexpr (BKC) {
-        floatx4 v = {0.f, 0.f, 0.f, 0.f};
-        if (n < N && k + 3 < kend) v = bl.load4(n, k, g);
-        else if (n < N)
-          for (int i = 0; i < 4; ++i)
-            if (k + i < kend) v[i] = bl(n, k + i, g);
-        rb[p][0] = pack_bf16(v[0], v[1]);
-        rb[p][1] = pack_bf16(v[2], v[3]);
       } else {
-        floatx4 v[8];
-        for (int j = 0; j < 8; ++j) {
-          v[j] = floatx4{0.f, 0.f, 0.f, 0.f};
-          if (k + j < kend) {
-            if (n + 3 < N) v[j] = bl.load4(n, k + j, g);
-            else
-              for (int i = 0; i < 4; ++i)
-                if (n + i < N) v[j][i] = bl(n + i, k + j, g);
-          }
-        }
-        for (int i = 0; i < 4; ++i)
-          for (int j = 0; j < 4; ++j) rb[p][4 * i + j] = pack_bf16(v[2 * j][i], v[2 * j + 1][i]);
+        for (int q = 0; q < QB; ++q) RB::fetch(bl, n, k + q, N, kend, g, rb[p][q], mb[p][q]);
       }
     }
   };
@@ -410,11 +351,14 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
       int row, kk;
       coordA(e, row, kk);
       if constexpr (AK) {
-        *reinterpret_cast<uint2 *>(&As[buf][sw(row, kk)]) = make_uint2(ra[p][0], ra[p][1]);
+        const floatx4 v = RA::finish(ra[p][0], ma[p][0]);
+        *reinterpret_cast<uint2 *>(&As[buf][sw(row, kk)]) = make_uint2(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]));
       } else {
+        floatx4 v[4];
+        for (int q = 0; q < 4; ++q) v[q] = RA::finish(ra[p][q], ma[p][q]);
         for (int i = 0; i < 4; ++i)
-          *reinterpret_cast<uint4 *>(&As[buf][sw(row + i, kk)]) =
-              make_uint4(ra[p][4 * i], ra[p][4 * i + 1], ra[p][4 * i + 2], ra[p][4 * i + 3]);
+          *reinterpret_cast<uint2 *>(&As[buf][sw(row + i, kk)]) =
+              make_uint2(pack_bf16(v[0][i], v[1][i]), pack_bf16(v[2][i], v[3][i]));
       }
     }
 #pragma unroll
@@ -423,12 +367,17 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
       if (e >= NB) continue;
       int col, kk;
       coordB(e, col, kk);
-      if constexpr (BKC) {
-        *reinterpret_cast<uint2 *>(&Bs[buf][sw(col, kk)]) = make_uint2(rb[p][0], rb[p][1]);
+      if constexpr (BT) {
+        *reinterpret_cast<uint2 *>(&Bs[buf][sw(col, kk)]) = rt[p];
+      } else if constexpr (BKC) {
+        const floatx4 v = RB::finish(rb[p][0], mb[p][0]);
+        *reinterpret_cast<uint2 *>(&Bs[buf][sw(col, kk)]) = make_uint2(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]));
       } else {
+        floatx4 v[4];
+        for (int q = 0; q < 4; ++q) v[q] = RB::finish(rb[p][q], mb[p][q]);
         for (int i = 0; i < 4; ++i)
-          *reinterpret_cast<uint4 *>(&Bs[buf][sw(col + i, kk)]) =
-              make_uint4(rb[p][4 * i], rb[p][4 * i + 1], rb[p][4 * i + 2], rb[p][4 * i + 3]);
+          *reinterpret_cast<uint2 *>(&Bs[buf][sw(col + i, kk)]) =
+              make_uint2(pack_bf16(v[0][i], v[1][i]), pack_bf16(v[2][i], v[3][i]));
       }
     }
   };
@@ -461,9 +410,6 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
     if (it + 1 < niter) stash(cur ^ 1);
     __syncthreads();
   }
-  // The MFMAs take the B fragment as their first operand, so each 16 x 16
-  // accumulator is the transposed tile: lane l holds row m = l % 16 and the
-  // four consecutive columns 4 (l / 16) .. +3, stored as one 16-byte run.
 #pragma unroll
   for (int i = 0; i < CF::TM; ++i) {
     const int64_t r = m0 + (wm * CF::TM + i) * 16 + q16;
@@ -528,29 +474,22 @@ static int run_gemm(AL al, BL bl, CS cs, int64_t M, int N, int K, int Z, int ksp
 }
 
 // ------------------------------------------------------- operand policies
-struct ARowMajor {
+template <bool MASK>
+struct ARowMajorT {
   static constexpr bool kContig = true;
+  static constexpr bool kMask = MASK;
   const float *A, *mask;
   int64_t lda, gs;
-  __device__ float operator()(int64_t r, int k, int g) const {
-    const int64_t o = r * lda + (int64_t)g * gs + k;
-    float v = A[o];
-    if (mask) v = mask[o] > 0.0f ? v : 0.0f;
-    return v;
-  }
-  __device__ floatx4 load4(int64_t r, int k, int g) const {
-    const int64_t o = r * lda + (int64_t)g * gs + k;
-    floatx4 v = ld4(A + o);
-    if (mask) {
-      const floatx4 m = ld4(mask + o);
-      for (int i = 0; i < 4; ++i) v[i] = m[i] > 0.0f ? v[i] : 0.0f;
-    }
-    return v;
-  }
+  __device__ float operator()(int64_t r, int k, int g) const { return A[r * lda + (int64_t)g * gs + k]; }
+  __device__ floatx4 load4(int64_t r, int k, int g) const { return ld4(A + r * lda + (int64_t)g * gs + k); }
+  __device__ float maskv(int64_t r, int k, int g) const { return mask[r * lda + (int64_t)g * gs + k]; }
+  __device__ floatx4 mask4(int64_t r, int k, int g) const { return ld4(mask + r * lda + (int64_t)g * gs + k); }
 };
+using ARowMajor = ARowMajorT<false>;
 
 struct BTableF {
   static constexpr bool kContig = true;
+  static constexpr bool kMask = false;
   using type = float;
   const float *B;
   int64_t gs;
@@ -561,6 +500,7 @@ struct BTableF {
 
 struct BTableH {
   static constexpr bool kContig = true;
+  static constexpr bool kMask = false;
   using type = uint16_t;
   const uint16_t *B;
   int64_t gs;
@@ -594,13 +534,18 @@ struct CRowMajor {
   }
 };
 
-template <int OP>
-static int table_gemm_op(const TableGemm &t, dlm_precision prec, hipStream_t st) {
+template <int OP, bool MASK>
+static int table_gemm_m(const TableGemm &t, dlm_precision prec, hipStream_t st) {
   const Shape sh = pick_shape(t.N);
   CRowMajor cs{t.C, t.ldc, t.c_gs, t.relu, t.bias_n};
-  ARowMajor al{t.A, t.mask, t.lda, t.a_gs};
+  ARowMajorT<MASK> al{t.A, t.mask, t.lda, t.a_gs};
   if (prec == DLM_BF16) return run_gemm_p<OP, true>(al, BTableH{t.Bh, t.b_gs, t.K}, cs, t.M, t.N, t.K, t.groups, 0, st, sh);
   return run_gemm_p<OP, false>(al, BTableF{t.Bf, t.b_gs, t.K}, cs, t.M, t.N, t.K, t.groups, 0, st, sh);
+}
+
+template <int OP>
+static int table_gemm_op(const TableGemm &t, dlm_precision prec, hipStream_t st) {
+  return t.mask ? table_gemm_m<OP, true>(t, prec, st) : table_gemm_m<OP, false>(t, prec, st);
 }
 
 int launch_table_gemm(const TableGemm &t, dlm_precision prec, void *stream) {
@@ -624,6 +569,7 @@ int launch_table_gemm(const TableGemm &t, dlm_precision prec, void *stream) {
 // Row r = (v, i) of the neighbourhood matrix; column k = (c, t).
 struct ANbhd {
   static constexpr bool kContig = true;
+  static constexpr bool kMask = false;
   const float *X;
   int m, T, C;
   __device__ float operator()(int64_t r, int k, int) const {
@@ -640,6 +586,7 @@ struct ANbhd {
 
 struct BWeightF {
   static constexpr bool kContig = true;
+  static constexpr bool kMask = false;
   using type = float;
   const float *W;
   int ld;
@@ -649,6 +596,7 @@ struct BWeightF {
 
 struct BWeightH {
   static constexpr bool kContig = true;
+  static constexpr bool kMask = false;
   using type = uint16_t;
   const uint16_t *W;
   int ld;
@@ -691,6 +639,7 @@ int launch_lsc_contract_fwd(const float *X, const float *W, const uint16_t *Wh, 
 // consecutive in memory.
 struct ADy {
   static constexpr bool kContig = false;
+  static constexpr bool kMask = false;
   const float *dy;
   int m, O;
   __device__ float operator()(int64_t r, int o, int) const {
@@ -734,6 +683,7 @@ int launch_lsc_contract_bwd_data(const float *dy, const float *Wt, const uint16_
 // columns n = o, reduction k = (v, i) split into `splits` slices.
 struct AXt {
   static constexpr bool kContig = false;
+  static constexpr bool kMask = false;
   const float *X;
   int m, T, C;
   __device__ float operator()(int64_t r, int k, int) const {
@@ -751,6 +701,7 @@ struct AXt {
 
 struct BDyT {
   static constexpr bool kContig = true;
+  static constexpr bool kMask = false;
   using type = float;
   const float *dy;
   int m, O;
@@ -807,6 +758,7 @@ int lsc_weight_splits(int64_t V, int m, int target) {
 // B(n = (k,j), t) = Q[t][k][j]: consecutive n are consecutive in memory.
 struct BQt {
   static constexpr bool kContig = false;
+  static constexpr bool kMask = false;
   using type = float;
   const float *Q;
   int KK;
@@ -858,29 +810,21 @@ int launch_lsc_bias_vec(const float *bias, const float *pm1, int O, int Ko, floa
 // plus a ones column (n = (c,j) or n = CK, giving the bias term).  Both
 // operands are contiguous along their row index, so the voxel index is the
 // strided one.  The larger of M and N1 is put on the GEMM's row side.
+template <bool MASK>
 struct AGradT {
   static constexpr bool kContig = false;
+  static constexpr bool kMask = MASK;
   const float *g, *mask;
   int M;
-  __device__ float operator()(int64_t m, int v, int) const {
-    const int64_t o = (int64_t)v * M + m;
-    float x = g[o];
-    if (mask) x = mask[o] > 0.0f ? x : 0.0f;
-    return x;
-  }
-  __device__ floatx4 load4(int64_t m, int v, int) const {
-    const int64_t o = (int64_t)v * M + m;
-    floatx4 x = ld4(g + o);
-    if (mask) {
-      const floatx4 k = ld4(mask + o);
-      for (int i = 0; i < 4; ++i) x[i] = k[i] > 0.0f ? x[i] : 0.0f;
-    }
-    return x;
-  }
+  __device__ float operator()(int64_t m, int v, int) const { return g[(int64_t)v * M + m]; }
+  __device__ floatx4 load4(int64_t m, int v, int) const { return ld4(g + (int64_t)v * M + m); }
+  __device__ float maskv(int64_t m, int v, int) const { return mask[(int64_t)v * M + m]; }
+  __device__ floatx4 mask4(int64_t m, int v, int) const { return ld4(mask + (int64_t)v * M + m); }
 };
 
 struct BActT {
   static constexpr bool kContig = false;
+  static constexpr bool kMask = false;
   using type = float;
   const float *a;
   int CK;
@@ -894,6 +838,7 @@ struct BActT {
 // transposed orientation: activations on the row side, gradient on the column side
 struct AActT {
   static constexpr bool kContig = false;
+  static constexpr bool kMask = false;
   const float *a;
   int CK;
   __device__ float operator()(int64_t n, int v, int) const { return n < CK ? a[(int64_t)v * CK + n] : 1.0f; }
@@ -903,26 +848,17 @@ struct AActT {
   }
 };
 
+template <bool MASK>
 struct BGradT {
   static constexpr bool kContig = false;
+  static constexpr bool kMask = MASK;
   using type = float;
   const float *g, *mask;
   int M;
-  __device__ float operator()(int m, int v, int) const {
-    const int64_t o = (int64_t)v * M + m;
-    float x = g[o];
-    if (mask) x = mask[o] > 0.0f ? x : 0.0f;
-    return x;
-  }
-  __device__ floatx4 load4(int m, int v, int) const {
-    const int64_t o = (int64_t)v * M + m;
-    floatx4 x = ld4(g + o);
-    if (mask) {
-      const floatx4 k = ld4(mask + o);
-      for (int i = 0; i < 4; ++i) x[i] = k[i] > 0.0f ? x[i] : 0.0f;
-    }
-    return x;
-  }
+  __device__ float operator()(int m, int v, int) const { return g[(int64_t)v * M + m]; }
+  __device__ floatx4 load4(int m, int v, int) const { return ld4(g + (int64_t)v * M + m); }
+  __device__ float maskv(int m, int v, int) const { return mask[(int64_t)v * M + m]; }
+  __device__ floatx4 mask4(int m, int v, int) const { return ld4(mask + (int64_t)v * M + m); }
 };
 
 template <bool TRANS>
@@ -972,11 +908,18 @@ int launch_lsc_fold_grad(const float *da_out, const float *mask, const float *a_
   if ((V + ks - 1) / ks != splits) return -2;
   hipStream_t st = (hipStream_t)stream;
   const Shape sh = grad_shape(M, N1);
-  if (M >= N1)
-    return run_gemm<kOpFoldGrad>(AGradT{da_out, mask, M}, BActT{a_in, CK}, CPartial2<false>{partial, M, N1}, M, N1,
+  if (M >= N1) {
+    if (mask)
+      return run_gemm<kOpFoldGrad>(AGradT<true>{da_out, mask, M}, BActT{a_in, CK}, CPartial2<false>{partial, M, N1}, M,
+                                   N1, (int)V, splits, ks, prec, st, sh);
+    return run_gemm<kOpFoldGrad>(AGradT<false>{da_out, nullptr, M}, BActT{a_in, CK}, CPartial2<false>{partial, M, N1},
+                                 M, N1, (int)V, splits, ks, prec, st, sh);
+  }
+  if (mask)
+    return run_gemm<kOpFoldGrad>(AActT{a_in, CK}, BGradT<true>{da_out, mask, M}, CPartial2<true>{partial, M, N1}, N1, M,
                                  (int)V, splits, ks, prec, st, sh);
-  return run_gemm<kOpFoldGrad>(AActT{a_in, CK}, BGradT{da_out, mask, M}, CPartial2<true>{partial, M, N1}, N1, M,
-                               (int)V, splits, ks, prec, st, sh);
+  return run_gemm<kOpFoldGrad>(AActT{a_in, CK}, BGradT<false>{da_out, nullptr, M}, CPartial2<true>{partial, M, N1}, N1,
+                               M, (int)V, splits, ks, prec, st, sh);
 }
 
 __global__ void sum_partials_kernel(const float *part, int splits, int64_t n, float *out) {
@@ -996,6 +939,7 @@ int launch_sum_partials(const float *part, int splits, int64_t n, float *out, vo
 // dTw viewed per (o,c): row r = (o,c), column k = (kk,j) of the Ko x Ki block.
 struct AUnfold {
   static constexpr bool kContig = true;
+  static constexpr bool kMask = false;
   const float *dTw;
   int C, Ki, Ko, N1;
   __device__ float operator()(int64_t r, int k, int) const {
@@ -1152,6 +1096,7 @@ int launch_b0_inverse_mean(const float *raw, int64_t ld, const int32_t *b0idx, i
 
 struct ARawNorm {
   static constexpr bool kContig = true;
+  static constexpr bool kMask = false;
   const float *raw;
   int64_t ld;
   const int32_t *dwidx;
