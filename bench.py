@@ -255,8 +255,11 @@ def main():
         dl.sh2signal_bwd(plan, dxhat, out=grads[-1], precision=prec)
         for k in range(len(layers) - 1, -1, -1):
             p, Wk, bk, relu = layers[k]
-            dl.lsc_bwd(p, acts[k], Wk, grads[k + 1], a_out=acts[k + 1], relu=relu, precision=prec, workspace=ws,
-                       outs=(grads[k], dWs[k], dbs[k]), form=form)
+            # the ReLU after layer k-1 is applied by layer k's adjoint as it writes grads[k]
+            relu_in = k > 0 and layers[k - 1][3]
+            relu_out = relu and k == len(layers) - 1
+            dl.lsc_bwd(p, acts[k], Wk, grads[k + 1], a_out=acts[k + 1], relu=relu_out, relu_in=relu_in,
+                       precision=prec, workspace=ws, outs=(grads[k], dWs[k], dbs[k]), form=form)
         dl.signal2sh_bwd(plan, grads[0], out=dx, precision=prec)
 
     for _ in range(args.warmup):

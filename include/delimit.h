@@ -185,18 +185,31 @@ dlm_status dlm_lsc_fwd(const dlm_lsc_plan *plan, const float *a_in, int C, const
                        const float *bias, int O, float *a_out, int64_t V, int fuse_relu,
                        dlm_lsc_form form, void *ws, size_t ws_bytes, dlm_precision prec, void *stream);
 
+/* ReLU handling of dlm_lsc_bwd (bit flags, 0 = no ReLU):
+ * DLM_RELU_OUT: this layer's forward fused a ReLU into a_out, and da_out is
+ *   the gradient of the ReLU's output: it is masked by a_out > 0 (a_out is
+ *   needed).
+ * DLM_RELU_IN: a_in is the output of the previous layer's fused ReLU; da_in
+ *   is written already masked by a_in > 0, i.e. as the gradient of that
+ *   layer's pre-activation, so the previous layer's dlm_lsc_bwd is then
+ *   called without DLM_RELU_OUT.  In a stack of layers this reads each ReLU
+ *   mask once (in the epilogue that writes da_in) instead of twice. */
+typedef enum { DLM_RELU_OUT = 1, DLM_RELU_IN = 2 } dlm_relu_flags;
+
 /* Adjoint of dlm_lsc_fwd.  da_out device [V][O][K_out] is the gradient of the
- * layer output; if fused_relu != 0 it is masked by a_out > 0 (a_out device
- * [V][O][K_out], the forward's output).  Outputs (each may be NULL to skip):
+ * layer output (masked by a_out > 0 under DLM_RELU_OUT, a_out device
+ * [V][O][K_out] the forward's output).  Outputs (each may be NULL to skip):
  *   da_in device [V][C][K_in]   = B_nb^T (sum_o W dy),  dy = P_m^T da
+ *                                 (times [a_in > 0] under DLM_RELU_IN)
  *   dW    device [O][C][T]      = sum_{v,i} dy[v][o][i] X[v][c][i*T+t] (overwritten)
  *   dbias device [O]            = sum_{v,i} dy[v][o][i]                (overwritten)
+ * relu_flags: a combination of dlm_relu_flags (other bits: DLM_EINVAL).
  * Resample form: the neighbourhood matrices X are recomputed from a_in, not
  * stored.  Folded form: dW comes from dT_oc = sum_v da_out[v][o] a_in[v][c]^T
  * contracted with each tap's (P_m B_t). */
 dlm_status dlm_lsc_bwd(const dlm_lsc_plan *plan, const float *a_in, int C, const float *W, int O,
                        const float *a_out, const float *da_out, float *da_in, float *dW, float *dbias,
-                       int64_t V, int fused_relu, dlm_lsc_form form, void *ws, size_t ws_bytes,
+                       int64_t V, int relu_flags, dlm_lsc_form form, void *ws, size_t ws_bytes,
                        dlm_precision prec, void *stream);
 
 /* ------------------------------------------------------------------------

@@ -291,8 +291,11 @@ def lsc_fwd(plan: LSCPlan, a_in: torch.Tensor, W: torch.Tensor, bias=None, relu:
 
 def lsc_bwd(plan: LSCPlan, a_in: torch.Tensor, W: torch.Tensor, da_out: torch.Tensor, a_out=None, relu=False,
             need_input_grad=True, need_weight_grad=True, need_bias_grad=True, precision="fp32",
-            workspace: Workspace | None = None, outs=None, form=DEFAULT_FORM):
+            workspace: Workspace | None = None, outs=None, form=DEFAULT_FORM, relu_in=False):
     """Returns (da_in or None, dW [O][C][T] or None, dbias [O] or None).
+    relu: the forward fused a ReLU into a_out (da_out is masked by a_out > 0).
+    relu_in: a_in is a ReLU output; da_in is returned masked by a_in > 0 (the
+    gradient of the previous layer's pre-activation).
     `outs` = (da_in, dW, dbias) preallocated float32 tensors (entries may be None)."""
     a_in = _f32_dev(a_in, "a_in")
     W = _f32_dev(W, "W").reshape(W.shape[0], W.shape[1], -1)
@@ -310,8 +313,9 @@ def lsc_bwd(plan: LSCPlan, a_in: torch.Tensor, W: torch.Tensor, da_out: torch.Te
     dW = (o_dW if o_dW is not None else torch.empty((O, Cin, plan.T), dtype=torch.float32, device=dev)) \
         if need_dW else None
     db = (o_db if o_db is not None else torch.empty((O,), dtype=torch.float32, device=dev)) if need_bias_grad else None
+    flags = (_lib.DLM_RELU_OUT if relu else 0) | (_lib.DLM_RELU_IN if relu_in else 0)
     check(lib().dlm_lsc_bwd(plan.handle, _ptr(a_in), Cin, _ptr(W), O, _ptr(a_out if relu else None), _ptr(da_out),
-                            _ptr(da_in), _ptr(dW), _ptr(db), V, int(bool(relu)), form_code(form), ws.ptr(),
+                            _ptr(da_in), _ptr(dW), _ptr(db), V, flags, form_code(form), ws.ptr(),
                             ws.nbytes, prec, _stream(a_in)))
     return da_in, (dW if need_weight_grad else None), db
 

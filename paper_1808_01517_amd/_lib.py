@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdelimit.
 DLM_OK, DLM_EINVAL, DLM_ESINGULAR, DLM_ENOMEM, DLM_EDEVICE, DLM_EWORKSPACE = range(6)
 DLM_FP32, DLM_BF16 = 0, 1
 DLM_LSC_RESAMPLE, DLM_LSC_FOLDED = 0, 1
+DLM_RELU_OUT, DLM_RELU_IN = 1, 2
 
 _p = C.c_void_p
 _dp = C.POINTER(C.c_double)

@@ -632,9 +632,13 @@ struct FoldWs {
 
 constexpr int kFoldSplitMax = 128;
 
+// bfloat16 copies of the folded matrices keep rows padded with zeros to a
+// multiple of 32 entries (the streaming core copies whole 32-entry slices)
+size_t pad32(size_t n) { return (n + 31) / 32 * 32; }
+
 size_t fold_ws_need(const dlm_lsc_plan *p, int C, int O) {
   const size_t M = size_t(O) * p->K_out, CK = size_t(C) * p->K_in, N1 = CK + 1;
-  return 2 * align256(M * CK * 4) + 2 * align256(M * CK * 2) + align256(M * 4) +
+  return 2 * align256(M * CK * 4) + align256(M * pad32(CK) * 2) + align256(CK * pad32(M) * 2) + align256(M * 4) +
          align256(size_t(kFoldSplitMax) * M * N1 * 4) + align256(M * N1 * 4);
 }
 
@@ -647,9 +651,9 @@ FoldWs fold_ws_carve(const dlm_lsc_plan *p, int C, int O, void *ws) {
   w.TwT = reinterpret_cast<float *>(b);
   b += align256(M * CK * 4);
   w.Twh = reinterpret_cast<uint16_t *>(b);
-  b += align256(M * CK * 2);
+  b += align256(M * pad32(CK) * 2);
   w.TwTh = reinterpret_cast<uint16_t *>(b);
-  b += align256(M * CK * 2);
+  b += align256(CK * pad32(M) * 2);
   w.bvec = reinterpret_cast<float *>(b);
   b += align256(M * 4);
   w.part = reinterpret_cast<float *>(b);
@@ -693,8 +697,12 @@ dlm_status fold_weights(const dlm_lsc_plan *p, int C, int O, const float *W, con
   {
     TimedScope ts("lsc_fold", stream, (double(O) * C * p->T + p->T * KK + 2.0 * M * CK) * 4.0,
                   2.0 * O * C * KK * p->T);
+    const size_t M_ = size_t(O) * p->K_out, CK_ = size_t(C) * p->K_in;
+    if (prec == DLM_BF16 && launch_zero(w.Twh, reinterpret_cast<char *>(w.TwTh) - reinterpret_cast<char *>(w.Twh) +
+                                                    CK_ * pad32(M_) * 2, stream) != 0)
+      return launched(-1);
     if (launch_lsc_fold(W, p->dQ.f32, C, O, p->T, p->K_in, p->K_out, w.Tw, w.TwT, prec == DLM_BF16 ? w.Twh : nullptr,
-                        prec == DLM_BF16 ? w.TwTh : nullptr, stream) != 0)
+                        prec == DLM_BF16 ? w.TwTh : nullptr, int64_t(pad32(CK_)), int64_t(pad32(M_)), stream) != 0)
       return launched(-1);
   }
   return launched(launch_lsc_bias_vec(bias, p->dpm1.f32, O, p->K_out, w.bvec, stream));
@@ -714,6 +722,7 @@ dlm_status lsc_fwd_folded(const dlm_lsc_plan *p, const float *a_in, int C, const
   t.lda = CK;
   t.Bf = w.Tw;
   t.Bh = w.Twh;
+  t.ldb_h = int64_t(pad32(size_t(CK)));
   t.C = a_out;
   t.ldc = M;
   t.bias_n = w.bvec;
@@ -727,7 +736,7 @@ dlm_status lsc_fwd_folded(const dlm_lsc_plan *p, const float *a_in, int C, const
 }
 
 dlm_status lsc_bwd_folded(const dlm_lsc_plan *p, const float *a_in, int C, const float *W, int O, const float *a_out,
-                          const float *da_out, float *da_in, float *dW, float *dbias, int64_t V, int fused_relu,
+                          const float *da_out, float *da_in, float *dW, float *dbias, int64_t V, int relu_flags,
                           void *ws, size_t ws_bytes, dlm_precision prec, void *stream) {
   if (ws_bytes < fold_ws_need(p, C, O))
     return fail(DLM_EWORKSPACE, "workspace of %zu bytes is below the %zu-byte minimum", ws_bytes, fold_ws_need(p, C, O));
@@ -735,7 +744,7 @@ dlm_status lsc_bwd_folded(const dlm_lsc_plan *p, const float *a_in, int C, const
   const int M = O * p->K_out, CK = C * p->K_in, N1 = CK + 1;
   if (dW && V > int64_t(0x7fffffff)) return fail(DLM_EINVAL, "V = %lld exceeds the 2^31-1 voxels of one call", (long long)V);
   dlm_status s;
-  const float *mask = fused_relu ? a_out : nullptr;
+  const float *mask = (relu_flags & DLM_RELU_OUT) ? a_out : nullptr;
   if (da_in && V > 0) {
     if ((s = fold_weights(p, C, O, W, nullptr, w, prec, stream)) != DLM_OK) return s;
     TableGemm t;  // da_in[v][(c,j)] = sum_{(o,k)} Tw[(o,k)][(c,j)] (da_out * [a_out > 0])[v][(o,k)]
@@ -744,13 +753,16 @@ dlm_status lsc_bwd_folded(const dlm_lsc_plan *p, const float *a_in, int C, const
     t.lda = M;
     t.Bf = w.TwT;
     t.Bh = w.TwTh;
+    t.ldb_h = int64_t(pad32(size_t(M)));
     t.C = da_in;
+    t.out_mask = (relu_flags & DLM_RELU_IN) ? a_in : nullptr;
     t.ldc = CK;
     t.M = V;
     t.N = CK;
     t.K = M;
     t.op = kOpFoldBwdData;
-    TimedScope ts("lsc_folded_bwd_data", stream, double(V) * (double(M) * (mask ? 2.0 : 1.0) + CK) * 4.0,
+    TimedScope ts("lsc_folded_bwd_data", stream,
+                  double(V) * (double(M) * (mask ? 2.0 : 1.0) + CK * (t.out_mask ? 2.0 : 1.0)) * 4.0,
                   2.0 * double(V) * M * CK);
     if ((s = launched(launch_table_gemm(t, prec, stream))) != DLM_OK) return s;
   }
@@ -845,18 +857,20 @@ dlm_status dlm_lsc_fwd(const dlm_lsc_plan *p, const float *a_in, int C, const fl
 }
 
 dlm_status dlm_lsc_bwd(const dlm_lsc_plan *p, const float *a_in, int C, const float *W, int O, const float *a_out,
-                       const float *da_out, float *da_in, float *dW, float *dbias, int64_t V, int fused_relu,
+                       const float *da_out, float *da_in, float *dW, float *dbias, int64_t V, int relu_flags,
                        dlm_lsc_form form, void *ws, size_t ws_bytes, dlm_precision prec, void *stream) {
   dlm_status s = lsc_check(p, C, O, V, prec);
   if (s != DLM_OK) return s;
   if (form != DLM_LSC_RESAMPLE && form != DLM_LSC_FOLDED) return fail(DLM_EINVAL, "unknown LSC form %d", int(form));
   if (!ws) return fail(DLM_EINVAL, "workspace is NULL");
-  if (fused_relu && !a_out && V > 0) return fail(DLM_EINVAL, "fused_relu needs the forward output a_out");
+  if (relu_flags & ~(DLM_RELU_OUT | DLM_RELU_IN)) return fail(DLM_EINVAL, "unknown relu flags 0x%x", relu_flags);
+  if ((relu_flags & DLM_RELU_OUT) && !a_out && V > 0)
+    return fail(DLM_EINVAL, "DLM_RELU_OUT needs the forward output a_out");
   if (dbias && !dW) return fail(DLM_EINVAL, "dbias without dW is not supported");
   if (V > 0 && (!a_in || !W || !da_out)) return fail(DLM_EINVAL, "null device pointer");
   if (form == DLM_LSC_FOLDED) {
     if (V > 0 && !W) return fail(DLM_EINVAL, "null device pointer");
-    s = lsc_bwd_folded(p, a_in, C, W, O, a_out, da_out, da_in, dW, dbias, V, fused_relu, ws, ws_bytes, prec, stream);
+    s = lsc_bwd_folded(p, a_in, C, W, O, a_out, da_out, da_in, dW, dbias, V, relu_flags, ws, ws_bytes, prec, stream);
     return s == DLM_OK ? ok() : s;
   }
   const int T = p->T, m = int(p->m);
@@ -888,7 +902,7 @@ dlm_status dlm_lsc_bwd(const dlm_lsc_plan *p, const float *a_in, int C, const fl
     const double dnv = double(nv);
     TableGemm rb;  // dy[(v,o)][i] = sum_k P_m[k][i] (da * [a_out > 0])[(v,o)][k]
     rb.A = da_out + v0 * O * p->K_out;
-    rb.mask = fused_relu ? a_out + v0 * O * p->K_out : nullptr;
+    rb.mask = (relu_flags & DLM_RELU_OUT) ? a_out + v0 * O * p->K_out : nullptr;
     rb.lda = p->K_out;
     rb.Bf = p->dPmT.f32;
     rb.Bh = p->dPmT.bf16;
@@ -899,7 +913,7 @@ dlm_status dlm_lsc_bwd(const dlm_lsc_plan *p, const float *a_in, int C, const fl
     rb.K = p->K_out;
     rb.op = kOpRefitBwd;
     {
-      TimedScope ts("lsc_refit_bwd", stream, dnv * O * (p->K_out * (fused_relu ? 2.0 : 1.0) + m) * 4.0,
+      TimedScope ts("lsc_refit_bwd", stream, dnv * O * (p->K_out * (rb.mask ? 2.0 : 1.0) + m) * 4.0,
                     2.0 * dnv * O * m * p->K_out);
       if ((s = launched(launch_table_gemm(rb, prec, stream))) != DLM_OK) return s;
     }
@@ -945,12 +959,13 @@ dlm_status dlm_lsc_bwd(const dlm_lsc_plan *p, const float *a_in, int C, const fl
       ra.Bf = p->dBnbT.f32;
       ra.Bh = p->dBnbT.bf16;
       ra.C = da_in + v0 * C * p->K_in;
+      ra.out_mask = (relu_flags & DLM_RELU_IN) ? a_in + v0 * C * p->K_in : nullptr;
       ra.ldc = p->K_in;
       ra.M = nv * C;
       ra.N = p->K_in;
       ra.K = int(P);
       ra.op = kOpResampleBwd;
-      TimedScope ts("lsc_resample_bwd", stream, dnv * C * (double(P) + p->K_in) * 4.0,
+      TimedScope ts("lsc_resample_bwd", stream, dnv * C * (double(P) + p->K_in * (ra.out_mask ? 2.0 : 1.0)) * 4.0,
                     2.0 * dnv * C * double(P) * p->K_in);
       if ((s = launched(launch_table_gemm(ra, prec, stream))) != DLM_OK) return s;
     }

@@ -20,17 +20,11 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "gemm_common.h"
 #include "internal.h"
 
 namespace dlm {
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-__device__ __forceinline__ uint16_t to_bf16_bits(float f) {
-  __bf16 h = (__bf16)f;  // hardware round-to-nearest-even conversion
-  return __builtin_bit_cast(uint16_t, h);
-}
 
 template <int BM_, int BN_, int WAVES_M_, int WAVES_N_>
 struct Cfg {
@@ -52,37 +46,7 @@ constexpr int lds_stride(int B) {
   return (B % 64 == 16 || B % 64 == 48) ? B : B + ((B % 64) < 16 ? 16 - B % 64 : (B % 64) < 48 ? 48 - B % 64 : 80 - B % 64);
 }
 
-// Block index -> (group / split z, M tile, N tile).  The grid is 1-D over
-// nbM * nbN * Z blocks, dispatched round-robin over the 8 XCDs; the block
-// index is remapped so that consecutive logical tiles land on one XCD and
-// share its L2.  Logical order: split-K (ZOUTER) puts all tiles of one voxel
-// slice together (they stream the same activation rows); grouped GEMMs put
-// the groups of one row-block together, then their N tiles.
-struct TileMap {
-  int mt, nt, z;
-  __device__ TileMap(int b, int nbM, int nbN, int Z, bool zouter) {
-    const int total = nbM * nbN * Z;
-    const int q = total >> 3, r = total & 7;
-    const int xcd = b & 7, local = b >> 3;
-    const int L = xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
-    if (zouter) {
-      z = L / (nbM * nbN);
-      const int t = L - z * nbM * nbN;
-      mt = t / nbN;
-      nt = t - mt * nbN;
-    } else {
-      nt = L % nbN;
-      z = (L / nbN) % Z;
-      mt = L / (nbN * Z);
-    }
-  }
-};
 
-__device__ __forceinline__ floatx4 ld4(const float *p) {
-  floatx4 v;
-  __builtin_memcpy(&v, p, 16);  // dword-aligned 16-byte load (global_load_dwordx4)
-  return v;
-}
 
 // Operand staging.  An operand is "k-contiguous" (kContig) or contiguous
 // along its row index.  Threads move runs of 4 elements along the
@@ -504,42 +468,24 @@ struct BTableH {
   using type = uint16_t;
   const uint16_t *B;
   int64_t gs;
-  int K;
-  __device__ uint16_t operator()(int n, int k, int g) const { return B[(int64_t)g * gs + (int64_t)n * K + k]; }
+  int64_t ld;  // row stride (>= K)
+  __device__ uint16_t operator()(int n, int k, int g) const { return B[(int64_t)g * gs + (int64_t)n * ld + k]; }
   __device__ uint2 load4h(int n, int k, int g) const {
     uint2 v;
-    __builtin_memcpy(&v, B + (int64_t)g * gs + (int64_t)n * K + k, 8);
+    __builtin_memcpy(&v, B + (int64_t)g * gs + (int64_t)n * ld + k, 8);
     return v;
   }
 };
 
-struct CRowMajor {
-  float *C;
-  int64_t ldc, gs;
-  int relu;
-  const float *bias_n;
-  __device__ void operator()(int64_t r, int n, int g, float v) const {
-    if (bias_n) v += bias_n[n];
-    if (relu) v = fmaxf(v, 0.0f);
-    C[r * ldc + (int64_t)g * gs + n] = v;
-  }
-  __device__ void store4(int64_t r, int n, int g, floatx4 v) const {
-    if (bias_n) {
-      const floatx4 b = ld4(bias_n + n);
-      for (int q = 0; q < 4; ++q) v[q] += b[q];
-    }
-    if (relu)
-      for (int q = 0; q < 4; ++q) v[q] = fmaxf(v[q], 0.0f);
-    __builtin_memcpy(C + r * ldc + (int64_t)g * gs + n, &v, 16);
-  }
-};
 
 template <int OP, bool MASK>
 static int table_gemm_m(const TableGemm &t, dlm_precision prec, hipStream_t st) {
   const Shape sh = pick_shape(t.N);
-  CRowMajor cs{t.C, t.ldc, t.c_gs, t.relu, t.bias_n};
+  CRowMajor cs{t.C, t.ldc, t.c_gs, t.relu, t.bias_n, t.out_mask};
   ARowMajorT<MASK> al{t.A, t.mask, t.lda, t.a_gs};
-  if (prec == DLM_BF16) return run_gemm_p<OP, true>(al, BTableH{t.Bh, t.b_gs, t.K}, cs, t.M, t.N, t.K, t.groups, 0, st, sh);
+  if (prec == DLM_BF16)
+    return run_gemm_p<OP, true>(al, BTableH{t.Bh, t.b_gs, t.ldb_h ? t.ldb_h : t.K}, cs, t.M, t.N, t.K, t.groups, 0, st,
+                                sh);
   return run_gemm_p<OP, false>(al, BTableF{t.Bf, t.b_gs, t.K}, cs, t.M, t.N, t.K, t.groups, 0, st, sh);
 }
 
@@ -549,6 +495,7 @@ static int table_gemm_op(const TableGemm &t, dlm_precision prec, hipStream_t st)
 }
 
 int launch_table_gemm(const TableGemm &t, dlm_precision prec, void *stream) {
+  if (prec == DLM_BF16 && stream_table_ok(t)) return launch_stream_table_bf16(t, stream);
   hipStream_t st = (hipStream_t)stream;
   switch (t.op) {
     case kOpS2shFwd: return table_gemm_op<kOpS2shFwd>(t, prec, st);
@@ -770,6 +717,7 @@ struct CFold {
   float *Tw, *TwT;
   uint16_t *Twh, *TwTh;
   int C, Ki, Ko, O;
+  int64_t ldh, ldth;
   __device__ void operator()(int64_t r, int n, int, float v) const {
     const int o = (int)r / C, c = (int)r - o * C;
     const int k = n / Ki, j = n - k * Ki;
@@ -777,8 +725,8 @@ struct CFold {
     const int64_t a = row * ((int64_t)C * Ki) + col, b = col * ((int64_t)O * Ko) + row;
     Tw[a] = v;
     TwT[b] = v;
-    if (Twh) Twh[a] = to_bf16_bits(v);
-    if (TwTh) TwTh[b] = to_bf16_bits(v);
+    if (Twh) Twh[row * ldh + col] = to_bf16_bits(v);
+    if (TwTh) TwTh[col * ldth + row] = to_bf16_bits(v);
   }
   __device__ void store4(int64_t r, int n, int g, floatx4 v) const {
     for (int q = 0; q < 4; ++q) (*this)(r, n + q, g, v[q]);
@@ -786,10 +734,24 @@ struct CFold {
 };
 
 int launch_lsc_fold(const float *W, const float *Q, int C, int O, int T, int Ki, int Ko, float *Tw, float *TwT,
-                    uint16_t *Twh, uint16_t *TwTh, void *stream) {
+                    uint16_t *Twh, uint16_t *TwTh, int64_t ldh, int64_t ldth, void *stream) {
   const int KK = Ko * Ki;
-  return run_gemm<kOpFoldMake>(ARowMajor{W, nullptr, T, 0}, BQt{Q, KK}, CFold{Tw, TwT, Twh, TwTh, C, Ki, Ko, O},
-                               (int64_t)O * C, KK, T, 1, 0, DLM_FP32, (hipStream_t)stream, pick_shape(KK));
+  return run_gemm<kOpFoldMake>(ARowMajor{W, nullptr, T, 0}, BQt{Q, KK},
+                               CFold{Tw, TwT, Twh, TwTh, C, Ki, Ko, O, ldh, ldth}, (int64_t)O * C, KK, T, 1, 0,
+                               DLM_FP32, (hipStream_t)stream, pick_shape(KK));
+}
+
+__global__ void zero_kernel(uint32_t *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+int launch_zero(void *p, size_t bytes, void *stream) {
+  const int64_t n = (int64_t)(bytes / 4);
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     static_cast<uint32_t *>(p), n);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 __global__ void bias_vec_kernel(const float *bias, const float *pm1, int O, int Ko, float *bvec) {
@@ -861,30 +823,14 @@ struct BGradT {
   __device__ floatx4 mask4(int m, int v, int) const { return ld4(mask + (int64_t)v * M + m); }
 };
 
-template <bool TRANS>
-struct CPartial2 {
-  float *part;
-  int M, N1;
-  __device__ void operator()(int64_t r, int c, int s, float v) const {
-    if constexpr (TRANS)
-      part[((int64_t)s * M + c) * N1 + r] = v;
-    else
-      part[((int64_t)s * M + r) * N1 + c] = v;
-  }
-  __device__ void store4(int64_t r, int c, int s, floatx4 v) const {
-    if constexpr (TRANS) {
-      for (int q = 0; q < 4; ++q) part[((int64_t)s * M + c + q) * N1 + r] = v[q];
-    } else {
-      __builtin_memcpy(part + ((int64_t)s * M + r) * N1 + c, &v, 16);
-    }
-  }
-};
 
 static int split_len(int64_t K, int splits) {
   const int bk = 32;
   int ks = (int)((K + splits - 1) / splits);
   return (ks + bk - 1) / bk * bk;
 }
+
+int fold_grad_split_len(int64_t V, int splits) { return split_len(V, splits); }
 
 static Shape grad_shape(int M, int N1) {
   // the smaller side (135/136 for the three-shell layers) fits one 144-wide
@@ -906,6 +852,7 @@ int launch_lsc_fold_grad(const float *da_out, const float *mask, const float *a_
   const int N1 = CK + 1;
   const int ks = split_len(V, splits);
   if ((V + ks - 1) / ks != splits) return -2;
+  if (prec == DLM_BF16 && !mask) return launch_stream_grad_bf16(da_out, a_in, V, M, CK, splits, ks, partial, stream);
   hipStream_t st = (hipStream_t)stream;
   const Shape sh = grad_shape(M, N1);
   if (M >= N1) {

@@ -1,0 +1,413 @@
+// Streaming BF16 GEMM core for the bandwidth-bound contractions of the
+// folded LSC layer (Sec. 2.3: resampling, cyclic-kernel dot and refit
+// composed into one matrix per layer) and its adjoints.
+//
+// In the BF16 form these contractions do 15-60 flop per HBM byte, far below
+// the bf16 matrix-core ridge (~300 flop/B), so this core is built to keep
+// HBM busy rather than the MFMA pipes:
+//
+// * Operands travel from global memory straight into LDS with
+//   global_load_lds_dword / _dwordx4 (no register staging), through a ring of
+//   NS stages, so NS-1 slices of 32 k are in flight while one is multiplied.
+// * Float32 operands stay float32 in LDS and are rounded to bfloat16 (RNE)
+//   when a wave reads its MFMA fragment; bfloat16 tables are copied as is.
+//   Reduction entries at or beyond the end of the range are zeroed at
+//   fragment read, so the DMA never has to zero-fill (it clamps addresses
+//   to valid elements instead).
+// * Every LDS layout is swizzled so that fragment reads avoid bank
+//   conflicts while each DMA instruction still fills 64 consecutive slots
+//   (the hardware writes lane i of an instruction to base + i * size).
+// * Waits are explicit: s_waitcnt vmcnt(n) for the slice about to be used,
+//   then a barrier.  A slot is refilled only after the barrier that follows
+//   its last read by every wave.
+//
+// MFMA: v_mfma_f32_16x16x32_bf16, B fragment first, so each accumulator is
+// the transposed 16 x 16 tile (a lane holds four consecutive output columns
+// of one row), the same epilogue as the register-staged cores.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "gemm_common.h"
+#include "internal.h"
+
+namespace dlm {
+namespace streaming {
+
+constexpr int SBK = 32;  // reduction entries per stage (one MFMA deep)
+
+#define DLM_LDS(p) ((__attribute__((address_space(3))) void *)(p))
+
+// Wait until at most N vector-memory operations of this wave are pending and
+// its LDS operations are complete, then join the workgroup barrier.
+template <int N>
+__device__ __forceinline__ void wait_barrier() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+// One DMA lane copy of SIZE bytes from global memory into LDS; the LDS
+// address of lane i is lds + i * SIZE (lds must be wave-uniform).  The
+// builtin is only legal in the gfx950 device pass (the 16-byte form is a
+// gfx950 instruction), so the host pass sees an empty body.
+template <int SIZE>
+__device__ __forceinline__ void dma_to_lds(const void *src, void *lds) {
+  static_assert(SIZE == 4 || SIZE == 16, "DMA lane size");
+#if defined(__HIP_DEVICE_COMPILE__)
+  if constexpr (SIZE == 16) __builtin_amdgcn_global_load_lds(src, DLM_LDS(lds), 16, 0, 0);
+  else __builtin_amdgcn_global_load_lds(src, DLM_LDS(lds), 4, 0, 0);
+#endif
+}
+
+__device__ __forceinline__ bf16x8 to_bf16x8(floatx4 lo, floatx4 hi) {
+  bf16x8 r;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    r[e] = (__bf16)lo[e];
+    r[4 + e] = (__bf16)hi[e];
+  }
+  return r;
+}
+
+// ------------------------------------------------------ streamed operands
+// Each operand type gives, for a tile of BR rows and one stage of SBK
+// reduction entries: bytes() of LDS, slots() DMA lanes of kUnit bytes,
+// src(slot) the global address the lane copies, and frag() the bfloat16
+// MFMA fragment of 16 rows (row group rg) x 8 k for lane (q16, g4):
+// row rg*16 + q16, k = 8*g4 .. 8*g4 + 7.
+
+// k-contiguous float32: element (r, k) at p[r * ld + k], valid for r < rows,
+// k < kend.  LDS: [BR][32] floats, 4-float chunk c of row r stored at chunk
+// c ^ (r & 7).  VEC (16-byte lanes) needs 16-byte aligned rows and kend % 4
+// == 0, so a chunk lies wholly inside or wholly beyond the range.
+template <bool VEC>
+struct SKc {
+  const float *p;
+  int64_t ld, rows;
+  static constexpr int kUnit = VEC ? 16 : 4;
+  template <int BR>
+  static constexpr int bytes() { return BR * SBK * 4; }
+  template <int BR>
+  static constexpr int slots() { return bytes<BR>() / kUnit; }
+  template <int BR>
+  __device__ const float *src(int s, int64_t r0, int k0, int kend) const {
+    int r, k;
+    if constexpr (VEC) {
+      r = s >> 3;
+      k = ((s & 7) ^ (r & 7)) << 2;
+    } else {
+      r = s >> 5;
+      k = ((((s >> 2) & 7) ^ (r & 7)) << 2) | (s & 3);
+    }
+    int64_t gr = r0 + r;
+    if (gr >= rows) gr = rows - 1;
+    int gk = k0 + k;
+    if (gk >= kend) gk = 0;
+    return p + gr * ld + gk;
+  }
+  template <int BR>
+  __device__ bf16x8 frag(const char *lds, int rg, int q16, int g4, int64_t, int k0, int kend, bool tail) const {
+    const int r = rg * 16 + q16;
+    const float *row = reinterpret_cast<const float *>(lds) + r * SBK;
+    floatx4 lo = *reinterpret_cast<const floatx4 *>(row + (((2 * g4) ^ (r & 7)) << 2));
+    floatx4 hi = *reinterpret_cast<const floatx4 *>(row + (((2 * g4 + 1) ^ (r & 7)) << 2));
+    if (tail) {
+      const int kb = k0 + 8 * g4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (kb + e >= kend) lo[e] = 0.0f;
+        if (kb + 4 + e >= kend) hi[e] = 0.0f;
+      }
+    }
+    return to_bf16x8(lo, hi);
+  }
+};
+
+// Row-contiguous float32: element (r, k) at p[k * ld + r], valid for
+// r < rows, k < kend; row `ones` (if >= 0) reads as 1 for k < kend.
+// LDS: [32][BR] floats (k-major); row r of k-line k is stored at
+// (r + 16 h(k)) mod BR with h(k) = bit 2 xor bit 3 of k, so the lanes of a
+// fragment read that differ in k land 16 banks apart.  VEC needs 16-byte
+// aligned k-lines and rows % 4 == 0.
+template <bool VEC>
+struct SRc {
+  const float *p;
+  int64_t ld, rows, ones;
+  static constexpr int kUnit = VEC ? 16 : 4;
+  template <int BR>
+  static constexpr int bytes() { return BR * SBK * 4; }
+  template <int BR>
+  static constexpr int slots() { return bytes<BR>() / kUnit; }
+  __device__ static int hk(int k) { return ((k >> 2) ^ (k >> 3)) & 1; }
+  template <int BR>
+  __device__ const float *src(int s, int64_t r0, int k0, int kend) const {
+    static_assert(BR % 16 == 0, "row tile");
+    int k, r;
+    if constexpr (VEC) {
+      constexpr int NC = BR / 4;
+      k = s / NC;
+      int rc = s - k * NC - 4 * hk(k);
+      if (rc < 0) rc += NC;
+      r = 4 * rc;
+    } else {
+      k = s / BR;
+      r = s - k * BR - 16 * hk(k);
+      if (r < 0) r += BR;
+    }
+    int64_t gr = r0 + r;
+    if (gr >= rows) gr = 0;
+    int gk = k0 + k;
+    if (gk >= kend) gk = kend - 1;
+    return p + (int64_t)gk * ld + gr;
+  }
+  template <int BR>
+  __device__ bf16x8 frag(const char *lds, int rg, int q16, int g4, int64_t r0, int k0, int kend, bool tail) const {
+    constexpr int NG = BR / 16;
+    const float *t = reinterpret_cast<const float *>(lds);
+    // h(8 g4 + e) = (e >> 2) ^ (g4 & 1): position group rg + h (mod NG)
+    const int nxt = rg + 1 == NG ? 0 : rg + 1;
+    const int glo = (g4 & 1) ? nxt : rg, ghi = (g4 & 1) ? rg : nxt;
+    floatx4 lo, hi;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      lo[e] = t[(8 * g4 + e) * BR + glo * 16 + q16];
+      hi[e] = t[(8 * g4 + 4 + e) * BR + ghi * 16 + q16];
+    }
+    const int kb = k0 + 8 * g4;
+    if (tail) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (kb + e >= kend) lo[e] = 0.0f;
+        if (kb + 4 + e >= kend) hi[e] = 0.0f;
+      }
+    }
+    const int64_t rbase = r0 + rg * 16;
+    if (ones >= rbase && ones < rbase + 16 && rbase + q16 == ones) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        lo[e] = kb + e < kend ? 1.0f : 0.0f;
+        hi[e] = kb + 4 + e < kend ? 1.0f : 0.0f;
+      }
+    }
+    return to_bf16x8(lo, hi);
+  }
+};
+
+// bfloat16 table: element (r, k) at p[r * ldp + k], ldp a multiple of 32,
+// entries k >= K stored as zeros.  LDS: [BR][32] bf16, 16-byte chunk c
+// (8 k) of row r stored at chunk c ^ ((r >> 1) & 3).
+struct SKh {
+  const uint16_t *p;
+  int64_t ldp, rows;
+  static constexpr int kUnit = 16;
+  template <int BR>
+  static constexpr int bytes() { return BR * SBK * 2; }
+  template <int BR>
+  static constexpr int slots() { return bytes<BR>() / kUnit; }
+  template <int BR>
+  __device__ const uint16_t *src(int s, int64_t r0, int k0, int) const {
+    const int r = s >> 2, c = (s & 3) ^ ((r >> 1) & 3);
+    int64_t gr = r0 + r;
+    if (gr >= rows) gr = rows - 1;
+    return p + gr * ldp + k0 + 8 * c;
+  }
+  template <int BR>
+  __device__ bf16x8 frag(const char *lds, int rg, int q16, int g4, int64_t, int, int, bool) const {
+    const int r = rg * 16 + q16;
+    return *reinterpret_cast<const bf16x8 *>(lds + r * 64 + ((g4 ^ ((r >> 1) & 3)) << 4));
+  }
+};
+
+// ------------------------------------------------------------------ core
+template <int BM_, int BN_, int WM_, int WN_, int NS_>
+struct SCfg {
+  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, NS = NS_;
+  static constexpr int TM = BM / (WM * 16), TN = BN / (WN * 16);
+  static_assert(WM * WN == 4, "four waves per block");
+  static_assert(TM * WM * 16 == BM && TN * WN * 16 == BN, "tile shape");
+  static_assert(NS >= 2 && NS <= 4, "ring depth");
+};
+
+template <int OP, class CF, class AO, class BO, class CS>
+__global__ __launch_bounds__(256) void gemm_stream_bf16_kernel(AO ao, BO bo, CS cs, int64_t M, int N, int K,
+                                                               int ksplit, int nbM, int nbN, int nz) {
+  constexpr int BM = CF::BM, BN = CF::BN;
+  constexpr int AB = AO::template bytes<BM>(), BB = BO::template bytes<BN>(), SB = AB + BB;
+  constexpr int NSA = AO::template slots<BM>(), NSB = BO::template slots<BN>();
+  constexpr int NIA = (NSA + 63) / 64, NIB = (NSB + 63) / 64;
+  // DMA instructions every wave issues per stage, at least (wave w issues
+  // instructions w, w + 4, ...); waits use this count, so a wave with more
+  // waits for slightly more than it needs.
+  constexpr int NIW = NIA / 4 + NIB / 4;
+  // ring depth: as configured while the pending count fits vmcnt (6 bits)
+  constexpr int NS = (CF::NS - 2) * NIW < 64 ? CF::NS : 2, D = NS - 1;
+  __shared__ __attribute__((aligned(16))) char lds[NS * SB];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave % CF::WM, wn = wave / CF::WM;
+  const int q16 = lane & 15, g4 = lane >> 4;
+  const TileMap tm(blockIdx.x, nbM, nbN, nz, ksplit > 0);
+  const int64_t m0 = (int64_t)tm.mt * BM;
+  const int n0 = tm.nt * BN;
+  const int z = tm.z;
+  int kbeg = 0, kend = K;
+  if (ksplit > 0) {
+    kbeg = z * ksplit;
+    kend = min(K, kbeg + ksplit);
+  }
+  const int niter = kend > kbeg ? (kend - kbeg + SBK - 1) / SBK : 0;
+
+  auto issue = [&](int it) {
+    char *sa = lds + (it % NS) * SB;
+    char *sb = sa + AB;
+    const int k0 = kbeg + it * SBK;
+#pragma unroll
+    for (int i = 0; i < (NIA + 3) / 4; ++i) {
+      const int inst = wave + 4 * i;
+      const int s = inst * 64 + lane;
+      if (inst < NIA && s < NSA)
+        dma_to_lds<AO::kUnit>(ao.template src<BM>(s, m0, k0, kend), sa + inst * 64 * AO::kUnit);
+    }
+#pragma unroll
+    for (int i = 0; i < (NIB + 3) / 4; ++i) {
+      const int inst = wave + 4 * i;
+      const int s = inst * 64 + lane;
+      if (inst < NIB && s < NSB)
+        dma_to_lds<BO::kUnit>(bo.template src<BN>(s, n0, k0, kend), sb + inst * 64 * BO::kUnit);
+    }
+  };
+
+  floatx4 acc[CF::TM][CF::TN];
+#pragma unroll
+  for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < CF::TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+  for (int s = 0; s < D; ++s)
+    if (s < niter) issue(s);
+  for (int it = 0; it < niter; ++it) {
+    const int after = min(D - 1, niter - 1 - it);  // stages issued after this one
+    if constexpr (D >= 3) {
+      if (after >= 2) wait_barrier<2 * NIW>();
+      else if (after == 1) wait_barrier<NIW>();
+      else wait_barrier<0>();
+    } else if constexpr (D == 2) {
+      if (after == 1) wait_barrier<NIW>();
+      else wait_barrier<0>();
+    } else {
+      wait_barrier<0>();
+    }
+    if (it + D < niter) issue(it + D);
+    const char *sa = lds + (it % NS) * SB;
+    const char *sb = sa + AB;
+    const int k0 = kbeg + it * SBK;
+    const bool tail = k0 + SBK > kend;
+    bf16x8 a[CF::TM], b[CF::TN];
+#pragma unroll
+    for (int i = 0; i < CF::TM; ++i) a[i] = ao.template frag<BM>(sa, wm * CF::TM + i, q16, g4, m0, k0, kend, tail);
+#pragma unroll
+    for (int j = 0; j < CF::TN; ++j) b[j] = bo.template frag<BN>(sb, wn * CF::TN + j, q16, g4, n0, k0, kend, tail);
+#pragma unroll
+    for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < CF::TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j], a[i], acc[i][j], 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < CF::TM; ++i) {
+    const int64_t r = m0 + (wm * CF::TM + i) * 16 + q16;
+    if (r >= M) continue;
+#pragma unroll
+    for (int j = 0; j < CF::TN; ++j) {
+      const int n = n0 + (wn * CF::TN + j) * 16 + 4 * g4;
+      if (n + 3 < N) {
+        cs.store4(r, n, z, acc[i][j]);
+      } else {
+        for (int q = 0; q < 4; ++q)
+          if (n + q < N) cs(r, n + q, z, acc[i][j][q]);
+      }
+    }
+  }
+}
+
+template <int OP, class CF, class AO, class BO, class CS>
+int run_stream(AO ao, BO bo, CS cs, int64_t M, int N, int K, int Z, int ksplit, hipStream_t st) {
+  if (M <= 0 || N <= 0 || Z <= 0) return 0;
+  const int64_t nbM = (M + CF::BM - 1) / CF::BM;
+  const int nbN = (N + CF::BN - 1) / CF::BN;
+  if (nbM * nbN * Z > 0x7fffffff) return -4;
+  hipLaunchKernelGGL((gemm_stream_bf16_kernel<OP, CF, AO, BO, CS>), dim3((unsigned)(nbM * nbN * Z)), dim3(256), 0, st,
+                     ao, bo, cs, M, N, K, ksplit, (int)nbM, nbN, Z);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+using SCfgWide = SCfg<128, 96, 2, 2, 3>;    // N = 1440, 2880: 15 / 30 tiles exactly
+using SCfgNarrow = SCfg<128, 144, 4, 1, 3>; // 96 < N <= 144 (N = 135, 136)
+using SCfgSmall = SCfg<128, 48, 4, 1, 3>;   // N <= 96
+
+template <int OP, class AO>
+int stream_table(AO ao, const TableGemm &t, hipStream_t st) {
+  const SKh bo{t.Bh, t.ldb_h, t.N};
+  const CRowMajor cs{t.C, t.ldc, 0, t.relu, t.bias_n, t.out_mask};
+  if (t.N <= 96) return run_stream<OP, SCfgSmall>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
+  if (t.N <= 144) return run_stream<OP, SCfgNarrow>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
+  return run_stream<OP, SCfgWide>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
+}
+
+template <int OP>
+int stream_table_op(const TableGemm &t, hipStream_t st) {
+  const bool vec = t.lda % 4 == 0 && t.K % 4 == 0 && aligned16(t.A);
+  if (vec) return stream_table<OP>(SKc<true>{t.A, t.lda, t.M}, t, st);
+  return stream_table<OP>(SKc<false>{t.A, t.lda, t.M}, t, st);
+}
+
+template <class AO, class BO, class CS>
+int stream_grad(AO ao, BO bo, CS cs, int64_t rows, int cols, int64_t V, int splits, int ks, hipStream_t st) {
+  return run_stream<kOpFoldGrad, SCfgNarrow>(ao, bo, cs, rows, cols, (int)V, splits, ks, st);
+}
+
+}  // namespace streaming
+
+using namespace streaming;
+
+bool stream_table_ok(const TableGemm &t) {
+  return t.groups == 1 && t.mask == nullptr && t.Bh != nullptr && t.ldb_h > 0 && t.ldb_h % SBK == 0 &&
+         t.ldb_h >= t.K && aligned16(t.Bh) && (t.op == kOpFoldFwd || t.op == kOpFoldBwdData);
+}
+
+int launch_stream_table_bf16(const TableGemm &t, void *stream) {
+  if (!stream_table_ok(t)) return -3;
+  hipStream_t st = (hipStream_t)stream;
+  switch (t.op) {
+    case kOpFoldFwd: return stream_table_op<kOpFoldFwd>(t, st);
+    case kOpFoldBwdData: return stream_table_op<kOpFoldBwdData>(t, st);
+    default: return -3;
+  }
+}
+
+// dT[m][n] = sum_v g[v][m] * act[v][n] over voxel slices, act with a ones
+// column at n = CK (the bias term); the larger of M and CK + 1 on the row side.
+int launch_stream_grad_bf16(const float *g, const float *a, int64_t V, int M, int CK, int splits, int ksplit,
+                            float *partial, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int N1 = CK + 1;
+  if (ksplit % SBK != 0) return -2;
+  const bool gv = M % 4 == 0 && aligned16(g), av = CK % 4 == 0 && aligned16(a);
+  if (M >= N1) {
+    const CPartial2<false> cs{partial, M, N1};
+    if (gv && av) return stream_grad(SRc<true>{g, M, M, -1}, SRc<true>{a, CK, CK, CK}, cs, M, N1, V, splits, ksplit, st);
+    if (gv) return stream_grad(SRc<true>{g, M, M, -1}, SRc<false>{a, CK, CK, CK}, cs, M, N1, V, splits, ksplit, st);
+    if (av) return stream_grad(SRc<false>{g, M, M, -1}, SRc<true>{a, CK, CK, CK}, cs, M, N1, V, splits, ksplit, st);
+    return stream_grad(SRc<false>{g, M, M, -1}, SRc<false>{a, CK, CK, CK}, cs, M, N1, V, splits, ksplit, st);
+  }
+  const CPartial2<true> cs{partial, M, N1};
+  if (gv && av) return stream_grad(SRc<true>{a, CK, CK, CK}, SRc<true>{g, M, M, -1}, cs, N1, M, V, splits, ksplit, st);
+  if (gv) return stream_grad(SRc<false>{a, CK, CK, CK}, SRc<true>{g, M, M, -1}, cs, N1, M, V, splits, ksplit, st);
+  if (av) return stream_grad(SRc<true>{a, CK, CK, CK}, SRc<false>{g, M, M, -1}, cs, N1, M, V, splits, ksplit, st);
+  return stream_grad(SRc<false>{a, CK, CK, CK}, SRc<false>{g, M, M, -1}, cs, N1, M, V, splits, ksplit, st);
+}
+
+}  // namespace dlm

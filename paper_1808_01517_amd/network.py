@@ -119,11 +119,18 @@ class LSCNetwork:
     def backward(self, V: int, need_input_grad=False):
         """Gradients of the last loss w.r.t. every weight (and the input when asked)."""
         sh2signal_bwd(self.plan_out, self.dxhat[:V], out=self.grads[-1][:V], precision=self.precision)
-        for k in range(len(self.specs) - 1, -1, -1):
+        n = len(self.specs)
+        for k in range(n - 1, -1, -1):
             s, p = self.specs[k], self.plans[k]
             if (k - 1) in self.recompute:
                 self._layer_fwd(k - 1, V)  # this layer's input was not kept: recompute it
-            lsc_bwd(p, self.acts[k][:V], self.W[k], self.grads[k + 1][:V], a_out=self.acts[k + 1][:V], relu=s.relu,
+            # A ReLU between layers k-1 and k is applied by layer k's adjoint as it
+            # writes the input gradient (the mask is read once); only a ReLU on the
+            # last layer's output would be masked by its own adjoint.
+            relu_in = k > 0 and self.specs[k - 1].relu
+            relu_out = s.relu and k == n - 1
+            lsc_bwd(p, self.acts[k][:V], self.W[k], self.grads[k + 1][:V],
+                    a_out=self.acts[k + 1][:V] if relu_out else None, relu=relu_out, relu_in=relu_in,
                     need_input_grad=(k > 0 or need_input_grad), precision=self.precision, workspace=self.ws,
                     outs=(self.grads[k][:V], self.dW[k], self.db[k]), form=self.form)
         if need_input_grad:

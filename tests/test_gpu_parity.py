@@ -10,6 +10,8 @@ import torch
 
 import datagen as dg
 import paper_1808_01517_amd as dl
+from paper_1808_01517_amd import _ptr as dptr
+from paper_1808_01517_amd._lib import DLM_EINVAL
 from oracle import lsc as olsc
 from oracle import sh as osh
 from oracle import stack as ostack
@@ -101,6 +103,42 @@ def test_lsc_forward_backward(prec, case, relu, form):
     assert rel(db, db_ref) <= TOL[prec]
 
 
+@pytest.mark.parametrize("form", ["resample", "folded"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("case", [(3, 32, 8, 8, (8, 8), 90, 203), (32, 3, 8, 8, (8, 8), 90, 203)])
+def test_lsc_backward_masks_input_gradient(prec, form, case):
+    # relu_in: the input gradient comes out multiplied by [a_in > 0] (the
+    # previous layer's ReLU); weight and bias gradients are unaffected
+    C, O, L_in, L_out, ks, m, V = case
+    oplan, plan, W, b, a = _lsc_case(C, O, L_in, L_out, ks, m, V, 6)
+    assert (a > 0).any() and (a <= 0).any()
+    da_out = np.random.default_rng(10).standard_normal((V, O, plan.K_out)).astype(np.float32).astype(np.float64)
+    _, z = olsc.lsc_forward(oplan, a, W, b, False)
+    da_ref, dW_ref, db_ref = olsc.lsc_backward(oplan, a, W, z, da_out, False)
+    da, dW, db = dl.lsc_bwd(plan, cuda(a), cuda(W), cuda(da_out), relu_in=True, precision=prec, form=form)
+    assert rel(da, da_ref * (a > 0)) <= TOL[prec]
+    assert rel(dW, dW_ref) <= TOL[prec]
+    assert rel(db, db_ref) <= TOL[prec]
+    masked = da.cpu().numpy()[a <= 0]
+    assert np.all(masked == 0.0)
+
+
+def test_lsc_backward_rejects_unknown_relu_flags():
+    C, O = 3, 4
+    _, plan, W, b, a = _lsc_case(C, O, 4, 4, (6, 6), 30, 8, 14)
+    ag, Wg = cuda(a), cuda(W)
+    g = torch.zeros((8, O, plan.K_out), device=DEV)
+    da = torch.empty_like(ag)
+    ws = dl.Workspace(dl.lsc_workspace_bytes(plan, C, O, 8, "fp32", "folded"), ag.device)
+    lib = dl.lib()
+    st = lib.dlm_lsc_bwd(plan.handle, dptr(ag), C, dptr(Wg), O, None, dptr(g), dptr(da), None, None, 8, 4,
+                         dl.DLM_LSC_FOLDED, ws.ptr(), ws.nbytes, dl.DLM_FP32, None)
+    assert st == DLM_EINVAL
+    st = lib.dlm_lsc_bwd(plan.handle, dptr(ag), C, dptr(Wg), O, None, dptr(g), dptr(da), None, None, 8, 1,
+                         dl.DLM_LSC_FOLDED, ws.ptr(), ws.nbytes, dl.DLM_FP32, None)
+    assert st == DLM_EINVAL  # DLM_RELU_OUT without a_out
+
+
 def test_lsc_chunked_workspace_matches_single_pass():
     # a workspace for 64 voxels forces several passes; results must agree with one pass
     C, O = 3, 32
@@ -151,9 +189,10 @@ def test_mse_and_adam():
     assert np.abs(wg.double().cpu().numpy() - ref).max() < 1e-6
 
 
+@pytest.mark.parametrize("mask_at", ["output", "input"])
 @pytest.mark.parametrize("form", ["resample", "folded"])
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_c2_stack_forward_backward(prec, form, c2_acq):
+def test_c2_stack_forward_backward(prec, form, mask_at, c2_acq):
     w = dg.C2
     V = 256 + 19
     acq = c2_acq
@@ -194,8 +233,11 @@ def test_c2_stack_forward_backward(prec, form, c2_acq):
     dWs, dbs = [None] * len(layers), [None] * len(layers)
     for k in range(len(layers) - 1, -1, -1):
         p, Wk, bk, relu = layers[k]
-        gcur, dWs[k], dbs[k] = dl.lsc_bwd(p, acts[k], Wk, gcur, a_out=acts[k + 1], relu=relu, precision=prec,
-                                          form=form)
+        if mask_at == "output":  # each layer masks its own output gradient
+            kw = dict(relu=relu)
+        else:  # each layer masks the input gradient it writes (the previous layer's ReLU)
+            kw = dict(relu=False, relu_in=k > 0 and layers[k - 1][3])
+        gcur, dWs[k], dbs[k] = dl.lsc_bwd(p, acts[k], Wk, gcur, a_out=acts[k + 1], precision=prec, form=form, **kw)
     dx = dl.signal2sh_bwd(plan, gcur, precision=prec)
     assert rel(dx, dx_ref) <= TOL[prec]
     for k in range(len(layers)):
