@@ -632,14 +632,16 @@ struct FoldWs {
 
 constexpr int kFoldSplitMax = 128;
 
-// bfloat16 copies of the folded matrices keep rows padded with zeros to a
-// multiple of 32 entries (the streaming core copies whole 32-entry slices)
+// The folded matrices (float32 and bfloat16 copies) keep rows padded with
+// zeros to a multiple of 32 entries: the streaming core copies whole
+// 32-entry slices.  Tw / Twh: [M][pad32(CK)]; TwT / TwTh: [CK][pad32(M)].
 size_t pad32(size_t n) { return (n + 31) / 32 * 32; }
 
 size_t fold_ws_need(const dlm_lsc_plan *p, int C, int O) {
   const size_t M = size_t(O) * p->K_out, CK = size_t(C) * p->K_in, N1 = CK + 1;
-  return 2 * align256(M * CK * 4) + align256(M * pad32(CK) * 2) + align256(CK * pad32(M) * 2) + align256(M * 4) +
-         align256(size_t(kFoldSplitMax) * M * N1 * 4) + align256(M * N1 * 4);
+  return align256(M * pad32(CK) * 4) + align256(CK * pad32(M) * 4) + align256(M * pad32(CK) * 2) +
+         align256(CK * pad32(M) * 2) + align256(M * 4) + align256(size_t(kFoldSplitMax) * M * N1 * 4) +
+         align256(M * N1 * 4);
 }
 
 FoldWs fold_ws_carve(const dlm_lsc_plan *p, int C, int O, void *ws) {
@@ -647,9 +649,9 @@ FoldWs fold_ws_carve(const dlm_lsc_plan *p, int C, int O, void *ws) {
   char *b = static_cast<char *>(ws);
   FoldWs w;
   w.Tw = reinterpret_cast<float *>(b);
-  b += align256(M * CK * 4);
+  b += align256(M * pad32(CK) * 4);
   w.TwT = reinterpret_cast<float *>(b);
-  b += align256(M * CK * 4);
+  b += align256(CK * pad32(M) * 4);
   w.Twh = reinterpret_cast<uint16_t *>(b);
   b += align256(M * pad32(CK) * 2);
   w.TwTh = reinterpret_cast<uint16_t *>(b);
@@ -698,8 +700,9 @@ dlm_status fold_weights(const dlm_lsc_plan *p, int C, int O, const float *W, con
     TimedScope ts("lsc_fold", stream, (double(O) * C * p->T + p->T * KK + 2.0 * M * CK) * 4.0,
                   2.0 * O * C * KK * p->T);
     const size_t M_ = size_t(O) * p->K_out, CK_ = size_t(C) * p->K_in;
-    if (prec == DLM_BF16 && launch_zero(w.Twh, reinterpret_cast<char *>(w.TwTh) - reinterpret_cast<char *>(w.Twh) +
-                                                    CK_ * pad32(M_) * 2, stream) != 0)
+    // zero the padding (all four tables are contiguous in the workspace)
+    if (launch_zero(w.Tw, reinterpret_cast<char *>(w.TwTh) - reinterpret_cast<char *>(w.Tw) + CK_ * pad32(M_) * 2,
+                    stream) != 0)
       return launched(-1);
     if (launch_lsc_fold(W, p->dQ.f32, C, O, p->T, p->K_in, p->K_out, w.Tw, w.TwT, prec == DLM_BF16 ? w.Twh : nullptr,
                         prec == DLM_BF16 ? w.TwTh : nullptr, int64_t(pad32(CK_)), int64_t(pad32(M_)), stream) != 0)
@@ -722,7 +725,7 @@ dlm_status lsc_fwd_folded(const dlm_lsc_plan *p, const float *a_in, int C, const
   t.lda = CK;
   t.Bf = w.Tw;
   t.Bh = w.Twh;
-  t.ldb_h = int64_t(pad32(size_t(CK)));
+  t.ldb_f = t.ldb_h = int64_t(pad32(size_t(CK)));
   t.C = a_out;
   t.ldc = M;
   t.bias_n = w.bvec;
@@ -753,7 +756,7 @@ dlm_status lsc_bwd_folded(const dlm_lsc_plan *p, const float *a_in, int C, const
     t.lda = M;
     t.Bf = w.TwT;
     t.Bh = w.TwTh;
-    t.ldb_h = int64_t(pad32(size_t(M)));
+    t.ldb_f = t.ldb_h = int64_t(pad32(size_t(M)));
     t.C = da_in;
     t.out_mask = (relu_flags & DLM_RELU_IN) ? a_in : nullptr;
     t.ldc = CK;

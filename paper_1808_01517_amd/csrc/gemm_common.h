@@ -51,12 +51,28 @@ struct TileMap {
 
 // C[r][n] (row stride ldc, group stride gs) = acc + bias_n[n], then an
 // optional ReLU, then (if omask) zeroed where omask (same indexing as C) <= 0.
+// Side inputs: colside (bias, per column) and elside (mask, per element) let
+// an epilogue load every tile's side values before its first store, so their
+// latency is paid once instead of once per store.
 struct CRowMajor {
+  static constexpr bool kSide = true;
   float *C;
   int64_t ldc, gs;
   int relu;
   const float *bias_n;
   const float *omask = nullptr;
+  __device__ floatx4 colside(int n) const { return bias_n ? ld4(bias_n + n) : floatx4{0.f, 0.f, 0.f, 0.f}; }
+  __device__ floatx4 elside(int64_t r, int n, int g) const {
+    return omask ? ld4(omask + r * ldc + (int64_t)g * gs + n) : floatx4{1.f, 1.f, 1.f, 1.f};
+  }
+  __device__ void store4s(int64_t r, int n, int g, floatx4 v, floatx4 cb, floatx4 em) const {
+    for (int q = 0; q < 4; ++q) {
+      v[q] += cb[q];
+      if (relu) v[q] = fmaxf(v[q], 0.0f);
+      v[q] = em[q] > 0.0f ? v[q] : 0.0f;
+    }
+    __builtin_memcpy(C + r * ldc + (int64_t)g * gs + n, &v, 16);
+  }
   __device__ void operator()(int64_t r, int n, int g, float v) const {
     const int64_t o = r * ldc + (int64_t)g * gs + n;
     if (bias_n) v += bias_n[n];
@@ -83,6 +99,7 @@ struct CRowMajor {
 
 template <bool TRANS>
 struct CPartial2 {
+  static constexpr bool kSide = false;
   float *part;
   int M, N1;
   __device__ void operator()(int64_t r, int c, int s, float v) const {

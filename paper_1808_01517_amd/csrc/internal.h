@@ -69,6 +69,7 @@ struct TableGemm {
   const float *Bf = nullptr;
   const uint16_t *Bh = nullptr;
   int64_t b_gs = 0;
+  int64_t ldb_f = 0;  // row stride of the float32 table (0: K)
   int64_t ldb_h = 0;  // row stride of the bfloat16 table (0: K)
   float *C = nullptr;
   const float *bias_n = nullptr;
@@ -81,14 +82,14 @@ struct TableGemm {
 };
 int launch_table_gemm(const TableGemm &g, dlm_precision prec, void *stream);
 
-// Streaming BF16 core (operands DMA'd into an LDS ring).  Table form: one
-// group, no operand mask, bfloat16 table with row stride ldb_h a multiple of
-// 32 and zeros in columns K .. ldb_h - 1.
-bool stream_table_ok(const TableGemm &g);
-int launch_stream_table_bf16(const TableGemm &g, void *stream);
+// Streaming core (operands DMA'd into an LDS ring).  Table form: one group,
+// no operand mask, the precision's table (float32 Bf / bfloat16 Bh) with row
+// stride ldb_f / ldb_h a multiple of 32 and zeros in columns K .. stride-1.
+bool stream_table_ok(const TableGemm &g, dlm_precision prec);
+int launch_stream_table(const TableGemm &g, dlm_precision prec, void *stream);
 // Weight-gradient form of launch_lsc_fold_grad (no mask), ksplit a multiple of 32.
-int launch_stream_grad_bf16(const float *g, const float *a, int64_t V, int M, int CK, int splits, int ksplit,
-                            float *partial, void *stream);
+int launch_stream_grad(const float *g, const float *a, int64_t V, int M, int CK, int splits, int ksplit,
+                       float *partial, dlm_precision prec, void *stream);
 // fill `bytes` (a multiple of 4) at p with zeros
 int launch_zero(void *p, size_t bytes, void *stream);
 
@@ -125,10 +126,10 @@ int launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float l
 
 // ----------------------------------------------------- folded LSC form
 // Tw[(o*Ko+k)][(c*Ki+j)] = sum_t W[o][c][t] Q[t][k][j]  (and the transpose
-// TwT[(c*Ki+j)][(o*Ko+k)]), float32 always, bfloat16 copies when non-null
-// with row strides ldh (Twh) and ldth (TwTh).
+// TwT[(c*Ki+j)][(o*Ko+k)]), float32 always, bfloat16 copies when non-null;
+// rows of Tw / Twh have stride ld, rows of TwT / TwTh stride ldt.
 int launch_lsc_fold(const float *W, const float *Q, int C, int O, int T, int Ki, int Ko, float *Tw, float *TwT,
-                    uint16_t *Twh, uint16_t *TwTh, int64_t ldh, int64_t ldth, void *stream);
+                    uint16_t *Twh, uint16_t *TwTh, int64_t ld, int64_t ldt, void *stream);
 int fold_grad_split_len(int64_t V, int splits);
 // bvec[o*Ko+k] = bias[o] * pm1[k]  (zero when bias is null)
 int launch_lsc_bias_vec(const float *bias, const float *pm1, int O, int Ko, float *bvec, void *stream);

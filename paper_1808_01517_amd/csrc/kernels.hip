@@ -457,9 +457,9 @@ struct BTableF {
   using type = float;
   const float *B;
   int64_t gs;
-  int K;
-  __device__ float operator()(int n, int k, int g) const { return B[(int64_t)g * gs + (int64_t)n * K + k]; }
-  __device__ floatx4 load4(int n, int k, int g) const { return ld4(B + (int64_t)g * gs + (int64_t)n * K + k); }
+  int64_t ld;  // row stride (>= K)
+  __device__ float operator()(int n, int k, int g) const { return B[(int64_t)g * gs + (int64_t)n * ld + k]; }
+  __device__ floatx4 load4(int n, int k, int g) const { return ld4(B + (int64_t)g * gs + (int64_t)n * ld + k); }
 };
 
 struct BTableH {
@@ -486,7 +486,8 @@ static int table_gemm_m(const TableGemm &t, dlm_precision prec, hipStream_t st) 
   if (prec == DLM_BF16)
     return run_gemm_p<OP, true>(al, BTableH{t.Bh, t.b_gs, t.ldb_h ? t.ldb_h : t.K}, cs, t.M, t.N, t.K, t.groups, 0, st,
                                 sh);
-  return run_gemm_p<OP, false>(al, BTableF{t.Bf, t.b_gs, t.K}, cs, t.M, t.N, t.K, t.groups, 0, st, sh);
+  return run_gemm_p<OP, false>(al, BTableF{t.Bf, t.b_gs, t.ldb_f ? t.ldb_f : t.K}, cs, t.M, t.N, t.K, t.groups, 0,
+                               st, sh);
 }
 
 template <int OP>
@@ -495,7 +496,7 @@ static int table_gemm_op(const TableGemm &t, dlm_precision prec, hipStream_t st)
 }
 
 int launch_table_gemm(const TableGemm &t, dlm_precision prec, void *stream) {
-  if (prec == DLM_BF16 && stream_table_ok(t)) return launch_stream_table_bf16(t, stream);
+  if (stream_table_ok(t, prec)) return launch_stream_table(t, prec, stream);
   hipStream_t st = (hipStream_t)stream;
   switch (t.op) {
     case kOpS2shFwd: return table_gemm_op<kOpS2shFwd>(t, prec, st);
@@ -717,16 +718,16 @@ struct CFold {
   float *Tw, *TwT;
   uint16_t *Twh, *TwTh;
   int C, Ki, Ko, O;
-  int64_t ldh, ldth;
+  int64_t ld, ldt;
   __device__ void operator()(int64_t r, int n, int, float v) const {
     const int o = (int)r / C, c = (int)r - o * C;
     const int k = n / Ki, j = n - k * Ki;
     const int64_t row = (int64_t)o * Ko + k, col = (int64_t)c * Ki + j;
-    const int64_t a = row * ((int64_t)C * Ki) + col, b = col * ((int64_t)O * Ko) + row;
+    const int64_t a = row * ld + col, b = col * ldt + row;
     Tw[a] = v;
     TwT[b] = v;
-    if (Twh) Twh[row * ldh + col] = to_bf16_bits(v);
-    if (TwTh) TwTh[col * ldth + row] = to_bf16_bits(v);
+    if (Twh) Twh[a] = to_bf16_bits(v);
+    if (TwTh) TwTh[b] = to_bf16_bits(v);
   }
   __device__ void store4(int64_t r, int n, int g, floatx4 v) const {
     for (int q = 0; q < 4; ++q) (*this)(r, n + q, g, v[q]);
@@ -734,10 +735,10 @@ struct CFold {
 };
 
 int launch_lsc_fold(const float *W, const float *Q, int C, int O, int T, int Ki, int Ko, float *Tw, float *TwT,
-                    uint16_t *Twh, uint16_t *TwTh, int64_t ldh, int64_t ldth, void *stream) {
+                    uint16_t *Twh, uint16_t *TwTh, int64_t ld, int64_t ldt, void *stream) {
   const int KK = Ko * Ki;
   return run_gemm<kOpFoldMake>(ARowMajor{W, nullptr, T, 0}, BQt{Q, KK},
-                               CFold{Tw, TwT, Twh, TwTh, C, Ki, Ko, O, ldh, ldth}, (int64_t)O * C, KK, T, 1, 0,
+                               CFold{Tw, TwT, Twh, TwTh, C, Ki, Ko, O, ld, ldt}, (int64_t)O * C, KK, T, 1, 0,
                                DLM_FP32, (hipStream_t)stream, pick_shape(KK));
 }
 
@@ -852,7 +853,7 @@ int launch_lsc_fold_grad(const float *da_out, const float *mask, const float *a_
   const int N1 = CK + 1;
   const int ks = split_len(V, splits);
   if ((V + ks - 1) / ks != splits) return -2;
-  if (prec == DLM_BF16 && !mask) return launch_stream_grad_bf16(da_out, a_in, V, M, CK, splits, ks, partial, stream);
+  if (!mask) return launch_stream_grad(da_out, a_in, V, M, CK, splits, ks, partial, prec, stream);
   hipStream_t st = (hipStream_t)stream;
   const Shape sh = grad_shape(M, N1);
   if (M >= N1) {

@@ -1,10 +1,12 @@
-// Streaming BF16 GEMM core for the bandwidth-bound contractions of the
-// folded LSC layer (Sec. 2.3: resampling, cyclic-kernel dot and refit
-// composed into one matrix per layer) and its adjoints.
+// Streaming GEMM core for the large contractions of the folded LSC layer
+// (Sec. 2.3: resampling, cyclic-kernel dot and refit composed into one
+// matrix per layer) and its adjoints.
 //
-// In the BF16 form these contractions do 15-60 flop per HBM byte, far below
-// the bf16 matrix-core ridge (~300 flop/B), so this core is built to keep
-// HBM busy rather than the MFMA pipes:
+// These contractions do 15-60 flop per HBM byte: far below the bf16
+// matrix-core ridge (~300 flop/B), so the BF16 form is bandwidth-bound,
+// and above the fp32 ridge (~20 flop/B), so the FP32 form is bound by the
+// fp32 MFMA rate.  Both want the operand traffic off the register file and
+// out of the way of the matrix cores:
 //
 // * Operands travel from global memory straight into LDS with
 //   global_load_lds_dword / _dwordx4 (no register staging), through a ring of
@@ -21,9 +23,15 @@
 //   then a barrier.  A slot is refilled only after the barrier that follows
 //   its last read by every wave.
 //
-// MFMA: v_mfma_f32_16x16x32_bf16, B fragment first, so each accumulator is
-// the transposed 16 x 16 tile (a lane holds four consecutive output columns
-// of one row), the same epilogue as the register-staged cores.
+// MFMA, B fragment first, so each accumulator is the transposed 16 x 16
+// tile (a lane holds four consecutive output columns of one row), the same
+// epilogue as the register-staged cores:
+//   BF16: v_mfma_f32_16x16x32_bf16, lane (q16, g4) holds k = 8 g4 .. 8 g4 + 7;
+//   FP32: v_mfma_f32_16x16x4_f32 over each 16-k group: lane (q16, g4) reads
+//         k = 4 g4 .. 4 g4 + 3 of the group at once and MFMA j takes k = 4 g4
+//         + j (a permutation of the reduction index, the same for A and B).
+// The ring is three stages deep in BF16 (latency-bound) and two in FP32
+// (one stage of fp32 MFMA work outlasts a load).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -121,6 +129,21 @@ struct SKc {
     }
     return to_bf16x8(lo, hi);
   }
+  // float32 values k = 16 h + 4 g4 .. + 3 of the stage for row rg*16 + q16
+  template <int BR>
+  __device__ floatx4 frag4(const char *lds, int rg, int q16, int g4, int64_t, int k0, int kend, bool tail,
+                           int h) const {
+    const int r = rg * 16 + q16;
+    const float *row = reinterpret_cast<const float *>(lds) + r * SBK;
+    floatx4 v = *reinterpret_cast<const floatx4 *>(row + (((4 * h + g4) ^ (r & 7)) << 2));
+    if (tail) {
+      const int kb = k0 + 16 * h + 4 * g4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (kb + e >= kend) v[e] = 0.0f;
+    }
+    return v;
+  }
 };
 
 // Row-contiguous float32: element (r, k) at p[k * ld + r], valid for
@@ -191,6 +214,30 @@ struct SRc {
     }
     return to_bf16x8(lo, hi);
   }
+  template <int BR>
+  __device__ floatx4 frag4(const char *lds, int rg, int q16, int g4, int64_t r0, int k0, int kend, bool tail,
+                           int h) const {
+    constexpr int NG = BR / 16;
+    const float *t = reinterpret_cast<const float *>(lds);
+    // k = 16 h + 4 g4 + j: h(k) = (g4 ^ (g4 >> 1)) & 1 for every j
+    int pg = rg + ((g4 ^ (g4 >> 1)) & 1);
+    if (pg == NG) pg = 0;
+    floatx4 v;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = t[(16 * h + 4 * g4 + j) * BR + pg * 16 + q16];
+    const int kb = k0 + 16 * h + 4 * g4;
+    if (tail) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (kb + j >= kend) v[j] = 0.0f;
+    }
+    const int64_t rbase = r0 + rg * 16;
+    if (ones >= rbase && ones < rbase + 16 && rbase + q16 == ones) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = kb + j < kend ? 1.0f : 0.0f;
+    }
+    return v;
+  }
 };
 
 // bfloat16 table: element (r, k) at p[r * ldp + k], ldp a multiple of 32,
@@ -228,19 +275,145 @@ struct SCfg {
   static_assert(NS >= 2 && NS <= 4, "ring depth");
 };
 
-template <int OP, class CF, class AO, class BO, class CS>
-__global__ __launch_bounds__(256) void gemm_stream_bf16_kernel(AO ao, BO bo, CS cs, int64_t M, int N, int K,
-                                                               int ksplit, int nbM, int nbN, int nz) {
+// One stage (32 k) of MFMAs for a consumer wave's TM x TN tiles.
+template <class CF, bool F32, class AO, class BO>
+__device__ __forceinline__ void mma_stage(const AO &ao, const BO &bo, const char *sa, const char *sb, int wm, int wn,
+                                          int q16, int g4, int64_t m0, int n0, int k0, int kend,
+                                          floatx4 (&acc)[CF::TM][CF::TN]) {
+  constexpr int BM = CF::BM, BN = CF::BN;
+  const bool tail = k0 + SBK > kend;
+  if constexpr (F32) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      floatx4 a[CF::TM], b[CF::TN];
+#pragma unroll
+      for (int i = 0; i < CF::TM; ++i)
+        a[i] = ao.template frag4<BM>(sa, wm * CF::TM + i, q16, g4, m0, k0, kend, tail, h);
+#pragma unroll
+      for (int j = 0; j < CF::TN; ++j)
+        b[j] = bo.template frag4<BN>(sb, wn * CF::TN + j, q16, g4, n0, k0, kend, tail, h);
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+        for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+          for (int j = 0; j < CF::TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[j][jj], a[i][jj], acc[i][j], 0, 0, 0);
+    }
+  } else {
+    bf16x8 a[CF::TM], b[CF::TN];
+#pragma unroll
+    for (int i = 0; i < CF::TM; ++i) a[i] = ao.template frag<BM>(sa, wm * CF::TM + i, q16, g4, m0, k0, kend, tail);
+#pragma unroll
+    for (int j = 0; j < CF::TN; ++j) b[j] = bo.template frag<BN>(sb, wn * CF::TN + j, q16, g4, n0, k0, kend, tail);
+#pragma unroll
+    for (int i = 0; i < CF::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < CF::TN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j], a[i], acc[i][j], 0, 0, 0);
+  }
+}
+
+// Store a consumer wave's tiles: lane (q16, g4) holds row m0 + (wm*TM+i)*16
+// + q16 and columns n0 + (wn*TN+j)*16 + 4 g4 .. + 3 of tile (i, j).
+template <class CF, class CS>
+__device__ __forceinline__ void store_tiles(const CS &cs, const floatx4 (&acc)[CF::TM][CF::TN], int64_t M, int N,
+                                            int64_t m0, int n0, int wm, int wn, int q16, int g4, int z) {
+  if constexpr (CS::kSide) {
+    // side inputs (bias, mask) of a chunk of tiles first, then its stores;
+    // chunks of RG tile rows keep the prefetched values within ~12 tiles
+    constexpr int RG = CF::TN >= 12 ? 1 : (12 / CF::TN < CF::TM ? 12 / CF::TN : CF::TM);
+    floatx4 cb[CF::TN];
+#pragma unroll
+    for (int j = 0; j < CF::TN; ++j) {
+      const int n = n0 + (wn * CF::TN + j) * 16 + 4 * g4;
+      cb[j] = n + 3 < N ? cs.colside(n) : floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int i0 = 0; i0 < CF::TM; i0 += RG) {
+      floatx4 em[RG][CF::TN];
+#pragma unroll
+      for (int ii = 0; ii < RG; ++ii) {
+        const int64_t r = m0 + (wm * CF::TM + i0 + ii) * 16 + q16;
+#pragma unroll
+        for (int j = 0; j < CF::TN; ++j) {
+          const int n = n0 + (wn * CF::TN + j) * 16 + 4 * g4;
+          em[ii][j] = i0 + ii < CF::TM && r < M && n + 3 < N ? cs.elside(r, n, z) : floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+      // Let the side loads land before the first store.  Without this the
+      // compiler may find one of them still pending at the next stage (on a
+      // path that stores nothing, e.g. rows beyond M) and wait there for every
+      // outstanding store too.  (vmcnt(0), expcnt and lgkmcnt untouched.)
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+#pragma unroll
+      for (int ii = 0; ii < RG; ++ii) {
+        const int i = i0 + ii;
+        if (i >= CF::TM) break;
+        const int64_t r = m0 + (wm * CF::TM + i) * 16 + q16;
+        if (r >= M) continue;
+#pragma unroll
+        for (int j = 0; j < CF::TN; ++j) {
+          const int n = n0 + (wn * CF::TN + j) * 16 + 4 * g4;
+          if (n + 3 < N) {
+            cs.store4s(r, n, z, acc[i][j], cb[j], em[ii][j]);
+          } else {
+            for (int q = 0; q < 4; ++q)
+              if (n + q < N) cs(r, n + q, z, acc[i][j][q]);
+          }
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < CF::TM; ++i) {
+      const int64_t r = m0 + (wm * CF::TM + i) * 16 + q16;
+      if (r >= M) continue;
+#pragma unroll
+      for (int j = 0; j < CF::TN; ++j) {
+        const int n = n0 + (wn * CF::TN + j) * 16 + 4 * g4;
+        if (n + 3 < N) {
+          cs.store4(r, n, z, acc[i][j]);
+        } else {
+          for (int q = 0; q < 4; ++q)
+            if (n + q < N) cs(r, n + q, z, acc[i][j][q]);
+        }
+      }
+    }
+  }
+}
+
+// DMA of one stage's share: instructions first, first + step, ... of the
+// operand's ceil(slots / 64) instructions.
+template <int BR, class OPND>
+__device__ __forceinline__ void dma_stage(const OPND &op, char *dst, int first, int step, int lane, int64_t r0, int k0,
+                                          int kend) {
+  constexpr int NSL = OPND::template slots<BR>();
+  constexpr int NI = (NSL + 63) / 64;
+#pragma unroll
+  for (int i = 0; i < (NI + step - 1) / step; ++i) {
+    const int inst = first + step * i;
+    const int s = inst * 64 + lane;
+    if (inst < NI && s < NSL) dma_to_lds<OPND::kUnit>(op.template src<BR>(s, r0, k0, kend), dst + inst * 64 * OPND::kUnit);
+  }
+}
+
+// One output tile (and one split-K slice) per block; all four waves issue
+// their share of every stage's DMA and compute.  Several blocks per CU keep
+// loads in flight while another block multiplies or stores.
+template <int OP, class CF, bool F32, class AO, class BO, class CS>
+__global__ __launch_bounds__(256) void gemm_stream_kernel(AO ao, BO bo, CS cs, int64_t M, int N, int K, int ksplit,
+                                                          int nbM, int nbN, int nz) {
   constexpr int BM = CF::BM, BN = CF::BN;
   constexpr int AB = AO::template bytes<BM>(), BB = BO::template bytes<BN>(), SB = AB + BB;
-  constexpr int NSA = AO::template slots<BM>(), NSB = BO::template slots<BN>();
-  constexpr int NIA = (NSA + 63) / 64, NIB = (NSB + 63) / 64;
+  constexpr int NIA = (AO::template slots<BM>() + 63) / 64, NIB = (BO::template slots<BN>() + 63) / 64;
   // DMA instructions every wave issues per stage, at least (wave w issues
   // instructions w, w + 4, ...); waits use this count, so a wave with more
   // waits for slightly more than it needs.
   constexpr int NIW = NIA / 4 + NIB / 4;
-  // ring depth: as configured while the pending count fits vmcnt (6 bits)
-  constexpr int NS = (CF::NS - 2) * NIW < 64 ? CF::NS : 2, D = NS - 1;
+  // ring depth: two stages in FP32; in BF16 as configured while the pending
+  // count fits vmcnt (6 bits)
+  constexpr int NS = F32 ? 2 : ((CF::NS - 2) * NIW < 64 ? CF::NS : 2), D = NS - 1;
   __shared__ __attribute__((aligned(16))) char lds[NS * SB];
 
   const int tid = threadIdx.x, lane = tid & 63;
@@ -260,22 +433,9 @@ __global__ __launch_bounds__(256) void gemm_stream_bf16_kernel(AO ao, BO bo, CS 
 
   auto issue = [&](int it) {
     char *sa = lds + (it % NS) * SB;
-    char *sb = sa + AB;
     const int k0 = kbeg + it * SBK;
-#pragma unroll
-    for (int i = 0; i < (NIA + 3) / 4; ++i) {
-      const int inst = wave + 4 * i;
-      const int s = inst * 64 + lane;
-      if (inst < NIA && s < NSA)
-        dma_to_lds<AO::kUnit>(ao.template src<BM>(s, m0, k0, kend), sa + inst * 64 * AO::kUnit);
-    }
-#pragma unroll
-    for (int i = 0; i < (NIB + 3) / 4; ++i) {
-      const int inst = wave + 4 * i;
-      const int s = inst * 64 + lane;
-      if (inst < NIB && s < NSB)
-        dma_to_lds<BO::kUnit>(bo.template src<BN>(s, n0, k0, kend), sb + inst * 64 * BO::kUnit);
-    }
+    dma_stage<BM>(ao, sa, wave, 4, lane, m0, k0, kend);
+    dma_stage<BN>(bo, sa + AB, wave, 4, lane, n0, k0, kend);
   };
 
   floatx4 acc[CF::TM][CF::TN];
@@ -301,113 +461,154 @@ __global__ __launch_bounds__(256) void gemm_stream_bf16_kernel(AO ao, BO bo, CS 
     }
     if (it + D < niter) issue(it + D);
     const char *sa = lds + (it % NS) * SB;
-    const char *sb = sa + AB;
-    const int k0 = kbeg + it * SBK;
-    const bool tail = k0 + SBK > kend;
-    bf16x8 a[CF::TM], b[CF::TN];
-#pragma unroll
-    for (int i = 0; i < CF::TM; ++i) a[i] = ao.template frag<BM>(sa, wm * CF::TM + i, q16, g4, m0, k0, kend, tail);
-#pragma unroll
-    for (int j = 0; j < CF::TN; ++j) b[j] = bo.template frag<BN>(sb, wn * CF::TN + j, q16, g4, n0, k0, kend, tail);
-#pragma unroll
-    for (int i = 0; i < CF::TM; ++i)
-#pragma unroll
-      for (int j = 0; j < CF::TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j], a[i], acc[i][j], 0, 0, 0);
+    mma_stage<CF, F32>(ao, bo, sa, sa + AB, wm, wn, q16, g4, m0, n0, kbeg + it * SBK, kend, acc);
   }
-#pragma unroll
-  for (int i = 0; i < CF::TM; ++i) {
-    const int64_t r = m0 + (wm * CF::TM + i) * 16 + q16;
-    if (r >= M) continue;
-#pragma unroll
-    for (int j = 0; j < CF::TN; ++j) {
-      const int n = n0 + (wn * CF::TN + j) * 16 + 4 * g4;
-      if (n + 3 < N) {
-        cs.store4(r, n, z, acc[i][j]);
-      } else {
-        for (int q = 0; q < 4; ++q)
-          if (n + q < N) cs(r, n + q, z, acc[i][j][q]);
-      }
-    }
-  }
+  store_tiles<CF>(cs, acc, M, N, m0, n0, wm, wn, q16, g4, z);
 }
 
-template <int OP, class CF, class AO, class BO, class CS>
+template <int OP, class CF, bool F32, class AO, class BO, class CS>
 int run_stream(AO ao, BO bo, CS cs, int64_t M, int N, int K, int Z, int ksplit, hipStream_t st) {
   if (M <= 0 || N <= 0 || Z <= 0) return 0;
   const int64_t nbM = (M + CF::BM - 1) / CF::BM;
   const int nbN = (N + CF::BN - 1) / CF::BN;
   if (nbM * nbN * Z > 0x7fffffff) return -4;
-  hipLaunchKernelGGL((gemm_stream_bf16_kernel<OP, CF, AO, BO, CS>), dim3((unsigned)(nbM * nbN * Z)), dim3(256), 0, st,
+  hipLaunchKernelGGL((gemm_stream_kernel<OP, CF, F32, AO, BO, CS>), dim3((unsigned)(nbM * nbN * Z)), dim3(256), 0, st,
                      ao, bo, cs, M, N, K, ksplit, (int)nbM, nbN, Z);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
+// Row-major output with compile-time side inputs: BIAS adds bias_n[n], MASK
+// zeroes entries where omask (indexed as C) <= 0; optional ReLU in between.
+template <bool BIAS, bool MASK>
+struct CRowSide {
+  static constexpr bool kSide = BIAS || MASK;
+  float *C;
+  int64_t ldc;
+  int relu;
+  const float *bias_n, *omask;
+  __device__ void operator()(int64_t r, int n, int, float v) const {
+    const int64_t o = r * ldc + n;
+    if constexpr (BIAS) v += bias_n[n];
+    if (relu) v = fmaxf(v, 0.0f);
+    if constexpr (MASK) v = omask[o] > 0.0f ? v : 0.0f;
+    C[o] = v;
+  }
+  __device__ void store4(int64_t r, int n, int g, floatx4 v) const {
+    for (int q = 0; q < 4; ++q) (*this)(r, n + q, g, v[q]);
+  }
+  __device__ floatx4 colside(int n) const {
+    if constexpr (BIAS) return ld4(bias_n + n);
+    else return floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+  __device__ floatx4 elside(int64_t r, int n, int) const {
+    if constexpr (MASK) return ld4(omask + r * ldc + n);
+    else return floatx4{1.f, 1.f, 1.f, 1.f};
+  }
+  __device__ void store4s(int64_t r, int n, int, floatx4 v, floatx4 cb, floatx4 em) const {
+    for (int q = 0; q < 4; ++q) {
+      if constexpr (BIAS) v[q] += cb[q];
+      if (relu) v[q] = fmaxf(v[q], 0.0f);
+      if constexpr (MASK) v[q] = em[q] > 0.0f ? v[q] : 0.0f;
+    }
+    __builtin_memcpy(C + r * ldc + n, &v, 16);
+  }
+};
+
 using SCfgWide = SCfg<128, 96, 2, 2, 3>;    // N = 1440, 2880: 15 / 30 tiles exactly
 using SCfgNarrow = SCfg<128, 144, 4, 1, 3>; // 96 < N <= 144 (N = 135, 136)
 using SCfgSmall = SCfg<128, 48, 4, 1, 3>;   // N <= 96
 
-template <int OP, class AO>
-int stream_table(AO ao, const TableGemm &t, hipStream_t st) {
-  const SKh bo{t.Bh, t.ldb_h, t.N};
-  const CRowMajor cs{t.C, t.ldc, 0, t.relu, t.bias_n, t.out_mask};
-  if (t.N <= 96) return run_stream<OP, SCfgSmall>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
-  if (t.N <= 144) return run_stream<OP, SCfgNarrow>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
-  return run_stream<OP, SCfgWide>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
+template <int OP, bool F32, class AO, class BO, class CS>
+int stream_table_c(AO ao, BO bo, CS cs, const TableGemm &t, hipStream_t st) {
+  if (t.N <= 96) return run_stream<OP, SCfgSmall, F32>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
+  if (t.N <= 144) return run_stream<OP, SCfgNarrow, F32>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
+  return run_stream<OP, SCfgWide, F32>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
 }
 
-template <int OP>
+// the forward GEMM adds the folded bias; the input-gradient GEMM may mask
+template <int OP, bool F32, class AO, class BO>
+int stream_table(AO ao, BO bo, const TableGemm &t, hipStream_t st) {
+  if constexpr (OP == kOpFoldFwd) {
+    return stream_table_c<OP, F32>(ao, bo, CRowSide<true, false>{t.C, t.ldc, t.relu, t.bias_n, nullptr}, t, st);
+  } else {
+    if (t.out_mask)
+      return stream_table_c<OP, F32>(ao, bo, CRowSide<false, true>{t.C, t.ldc, t.relu, nullptr, t.out_mask}, t, st);
+    return stream_table_c<OP, F32>(ao, bo, CRowSide<false, false>{t.C, t.ldc, t.relu, nullptr, nullptr}, t, st);
+  }
+}
+
+template <int OP, bool F32, class AO>
+int stream_table_b(AO ao, const TableGemm &t, hipStream_t st) {
+  // float32 tables are read as k-contiguous float32 rows of stride ldb_f
+  if constexpr (F32) return stream_table<OP, true>(ao, SKc<true>{t.Bf, t.ldb_f, t.N}, t, st);
+  else return stream_table<OP, false>(ao, SKh{t.Bh, t.ldb_h, t.N}, t, st);
+}
+
+template <int OP, bool F32>
 int stream_table_op(const TableGemm &t, hipStream_t st) {
   const bool vec = t.lda % 4 == 0 && t.K % 4 == 0 && aligned16(t.A);
-  if (vec) return stream_table<OP>(SKc<true>{t.A, t.lda, t.M}, t, st);
-  return stream_table<OP>(SKc<false>{t.A, t.lda, t.M}, t, st);
+  if (vec) return stream_table_b<OP, F32>(SKc<true>{t.A, t.lda, t.M}, t, st);
+  return stream_table_b<OP, F32>(SKc<false>{t.A, t.lda, t.M}, t, st);
 }
 
-template <class AO, class BO, class CS>
+template <bool F32, class AO, class BO, class CS>
 int stream_grad(AO ao, BO bo, CS cs, int64_t rows, int cols, int64_t V, int splits, int ks, hipStream_t st) {
-  return run_stream<kOpFoldGrad, SCfgNarrow>(ao, bo, cs, rows, cols, (int)V, splits, ks, st);
+  return run_stream<kOpFoldGrad, SCfgNarrow, F32>(ao, bo, cs, rows, cols, (int)V, splits, ks, st);
 }
 
 }  // namespace streaming
 
 using namespace streaming;
 
-bool stream_table_ok(const TableGemm &t) {
-  return t.groups == 1 && t.mask == nullptr && t.Bh != nullptr && t.ldb_h > 0 && t.ldb_h % SBK == 0 &&
-         t.ldb_h >= t.K && aligned16(t.Bh) && (t.op == kOpFoldFwd || t.op == kOpFoldBwdData);
+bool stream_table_ok(const TableGemm &t, dlm_precision prec) {
+  if (t.groups != 1 || t.mask != nullptr || (t.op != kOpFoldFwd && t.op != kOpFoldBwdData)) return false;
+  if (t.op == kOpFoldFwd ? (t.bias_n == nullptr || t.out_mask != nullptr) : t.bias_n != nullptr) return false;
+  if (prec == DLM_BF16)
+    return t.Bh != nullptr && t.ldb_h > 0 && t.ldb_h % SBK == 0 && t.ldb_h >= t.K && aligned16(t.Bh);
+  return t.Bf != nullptr && t.ldb_f > 0 && t.ldb_f % SBK == 0 && t.ldb_f >= t.K && aligned16(t.Bf);
 }
 
-int launch_stream_table_bf16(const TableGemm &t, void *stream) {
-  if (!stream_table_ok(t)) return -3;
+int launch_stream_table(const TableGemm &t, dlm_precision prec, void *stream) {
+  if (!stream_table_ok(t, prec)) return -3;
   hipStream_t st = (hipStream_t)stream;
+  const bool f32 = prec != DLM_BF16;
   switch (t.op) {
-    case kOpFoldFwd: return stream_table_op<kOpFoldFwd>(t, st);
-    case kOpFoldBwdData: return stream_table_op<kOpFoldBwdData>(t, st);
+    case kOpFoldFwd: return f32 ? stream_table_op<kOpFoldFwd, true>(t, st) : stream_table_op<kOpFoldFwd, false>(t, st);
+    case kOpFoldBwdData:
+      return f32 ? stream_table_op<kOpFoldBwdData, true>(t, st) : stream_table_op<kOpFoldBwdData, false>(t, st);
     default: return -3;
   }
 }
 
 // dT[m][n] = sum_v g[v][m] * act[v][n] over voxel slices, act with a ones
 // column at n = CK (the bias term); the larger of M and CK + 1 on the row side.
-int launch_stream_grad_bf16(const float *g, const float *a, int64_t V, int M, int CK, int splits, int ksplit,
-                            float *partial, void *stream) {
-  hipStream_t st = (hipStream_t)stream;
+template <bool F32>
+static int stream_grad_p(const float *g, const float *a, int64_t V, int M, int CK, int splits, int ksplit,
+                         float *partial, hipStream_t st) {
   const int N1 = CK + 1;
-  if (ksplit % SBK != 0) return -2;
   const bool gv = M % 4 == 0 && aligned16(g), av = CK % 4 == 0 && aligned16(a);
   if (M >= N1) {
     const CPartial2<false> cs{partial, M, N1};
-    if (gv && av) return stream_grad(SRc<true>{g, M, M, -1}, SRc<true>{a, CK, CK, CK}, cs, M, N1, V, splits, ksplit, st);
-    if (gv) return stream_grad(SRc<true>{g, M, M, -1}, SRc<false>{a, CK, CK, CK}, cs, M, N1, V, splits, ksplit, st);
-    if (av) return stream_grad(SRc<false>{g, M, M, -1}, SRc<true>{a, CK, CK, CK}, cs, M, N1, V, splits, ksplit, st);
-    return stream_grad(SRc<false>{g, M, M, -1}, SRc<false>{a, CK, CK, CK}, cs, M, N1, V, splits, ksplit, st);
+    if (gv && av) return stream_grad<F32>(SRc<true>{g, M, M, -1}, SRc<true>{a, CK, CK, CK}, cs, M, N1, V, splits, ksplit, st);
+    if (gv) return stream_grad<F32>(SRc<true>{g, M, M, -1}, SRc<false>{a, CK, CK, CK}, cs, M, N1, V, splits, ksplit, st);
+    if (av) return stream_grad<F32>(SRc<false>{g, M, M, -1}, SRc<true>{a, CK, CK, CK}, cs, M, N1, V, splits, ksplit, st);
+    return stream_grad<F32>(SRc<false>{g, M, M, -1}, SRc<false>{a, CK, CK, CK}, cs, M, N1, V, splits, ksplit, st);
   }
   const CPartial2<true> cs{partial, M, N1};
-  if (gv && av) return stream_grad(SRc<true>{a, CK, CK, CK}, SRc<true>{g, M, M, -1}, cs, N1, M, V, splits, ksplit, st);
-  if (gv) return stream_grad(SRc<false>{a, CK, CK, CK}, SRc<true>{g, M, M, -1}, cs, N1, M, V, splits, ksplit, st);
-  if (av) return stream_grad(SRc<true>{a, CK, CK, CK}, SRc<false>{g, M, M, -1}, cs, N1, M, V, splits, ksplit, st);
-  return stream_grad(SRc<false>{a, CK, CK, CK}, SRc<false>{g, M, M, -1}, cs, N1, M, V, splits, ksplit, st);
+  if (gv && av) return stream_grad<F32>(SRc<true>{a, CK, CK, CK}, SRc<true>{g, M, M, -1}, cs, N1, M, V, splits, ksplit, st);
+  if (gv) return stream_grad<F32>(SRc<false>{a, CK, CK, CK}, SRc<true>{g, M, M, -1}, cs, N1, M, V, splits, ksplit, st);
+  if (av) return stream_grad<F32>(SRc<true>{a, CK, CK, CK}, SRc<false>{g, M, M, -1}, cs, N1, M, V, splits, ksplit, st);
+  return stream_grad<F32>(SRc<false>{a, CK, CK, CK}, SRc<false>{g, M, M, -1}, cs, N1, M, V, splits, ksplit, st);
+}
+
+int launch_stream_grad(const float *g, const float *a, int64_t V, int M, int CK, int splits, int ksplit,
+                       float *partial, dlm_precision prec, void *stream) {
+  if (ksplit % SBK != 0) return -2;
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == DLM_BF16) return stream_grad_p<false>(g, a, V, M, CK, splits, ksplit, partial, st);
+  return stream_grad_p<true>(g, a, V, M, CK, splits, ksplit, partial, st);
 }
 
 }  // namespace dlm
