@@ -77,6 +77,38 @@ def make_data(w, V, chunk=1 << 16):
     return acq, x, clean
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_stack_folded_hbm_traffic.txt")
+
+
+def kernel_source_hash():
+    """sha256 prefix of the library's kernel and launch sources (as recorded with the counters)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1808_01517_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(tag, prec):
+    """HBM bytes per launch of `tag` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary, or None when that summary was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            lines = [ln.split() for ln in fh if ln.strip() and not ln.startswith("#")]
+    except OSError:
+        return None
+    recorded = next((ln[1] for ln in lines if ln[0] == "source_sha256"), None)
+    if recorded != kernel_source_hash():
+        return None
+    for ln in lines:
+        if ln[0] == "traffic" and ln[1] == prec and ln[2] == tag:
+            return float(ln[3])
+    return None
+
+
 def roofline(tag, ms, launches, nbytes, flops, prec):
     t = ms / 1e3
     hbm_time = nbytes / (HBM_PEAK_GBS * 1e9)
@@ -115,11 +147,12 @@ def cpu_baseline(w, acq, target_s):
         W, b = dg.lsc_weights(w.config, k, ch[k], ch[k + 1], p.T)
         layers.append(ostack.Layer(p, W, b, k < len(ch) - 2))
     net = ostack.Stack(plan, layers, plan)
-    batch = dg.stick_ball_batch(acq, 4096, w.nf_max, w.snr, dg.rng_for(w.config, dg.STREAM_HELDOUT, 0))
+    nmax = 16384
+    batch = dg.stick_ball_batch(acq, nmax, w.nf_max, w.snr, dg.rng_for(w.config, dg.STREAM_HELDOUT, 0))
     t0 = time.perf_counter()
     net.loss_and_grads(batch.x[:128], batch.clean[:128])
     per_vox = (time.perf_counter() - t0) / 128
-    n = int(min(4096, max(256, target_s / max(per_vox, 1e-9))))
+    n = int(min(nmax, max(256, target_s / max(per_vox, 1e-9))))
     n = (n // 256) * 256
     t0 = time.perf_counter()
     for lo in range(0, n, 1024):
@@ -305,6 +338,10 @@ def main():
                 for t, v in sorted(rep.items(), key=lambda kv: -kv[1][0])}
         top = max(rep.items(), key=lambda kv: kv[1][0])
         result["roofline"] = roofline(top[0], *top[1], prec)
+        if form == "folded" and V == w.voxels:
+            # counters were taken on this workload in the folded form only
+            result["roofline"]["traffic"] = measured_traffic(top[0], prec)
+            result["roofline"]["traffic_source"] = os.path.relpath(TRAFFIC_FILE, ROOT)
         roof_s = sum(max(v[2] / (HBM_PEAK_GBS * 1e9), v[3] / (MFMA_PEAK_TFLOPS[prec] * 1e12)) for v in rep.values())
         result["step_roofline_frac"] = round(roof_s / args.steps / (ms_step / 1e3), 4)
         result["kernels"] = kern

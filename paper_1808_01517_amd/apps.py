@@ -163,6 +163,7 @@ def run_learned(train_voxels=1 << 22, eval_voxels=262144, epochs=8, lr=2e-3, bat
         print(f"[learned] epoch {ep + 1}/{epochs} loss {float(net.loss):.6f} "
               f"({time.perf_counter() - t_train:.1f} s)", file=log, flush=True)
     train_s = time.perf_counter() - t_train
+    final_loss = float(net.loss)  # evaluation below may reallocate the network's buffers
     torch.cuda.synchronize()
     t_inf = time.perf_counter()
     pred = predict(S, xs_ev)
@@ -178,7 +179,7 @@ def run_learned(train_voxels=1 << 22, eval_voxels=262144, epochs=8, lr=2e-3, bat
         "nrmse_fit_lambda0_vs_clean": nrmse(fit0, y_ev),
         "nrmse_net_vs_noisy": nrmse(pred, x_ev_full), "nrmse_fit_vs_noisy": nrmse(fit, x_ev_full),
         "train_voxels_per_s": steps * batch / train_s, "inference_voxels_per_s": eval_voxels / inf_s,
-        "final_train_loss": float(net.loss),
+        "final_train_loss": final_loss,
     }
     return res, S, net
 
