@@ -13,9 +13,12 @@
 //   NS stages, so NS-1 slices of 32 k are in flight while one is multiplied.
 // * Float32 operands stay float32 in LDS and are rounded to bfloat16 (RNE)
 //   when a wave reads its MFMA fragment; bfloat16 tables are copied as is.
-//   Reduction entries at or beyond the end of the range are zeroed at
-//   fragment read, so the DMA never has to zero-fill (it clamps addresses
-//   to valid elements instead).
+//   Lanes whose reduction index lies at or beyond the end of the range copy
+//   zeros from a 4 KB zero buffer (spread over lanes, so no single cache
+//   line is hot); the weight gradient's ones row is written into every ring
+//   slot once at kernel start and skipped by the DMA.  LDS thus holds the
+//   exact operands and fragment reads need no conditionals.  Rows beyond the
+//   matrix are clamped to valid rows (their outputs are never stored).
 // * Every LDS layout is swizzled so that fragment reads avoid bank
 //   conflicts while each DMA instruction still fills 64 consecutive slots
 //   (the hardware writes lane i of an instruction to base + i * size).
@@ -45,6 +48,10 @@ namespace streaming {
 constexpr int SBK = 32;  // reduction entries per stage (one MFMA deep)
 
 #define DLM_LDS(p) ((__attribute__((address_space(3))) void *)(p))
+
+// Source of the DMA lanes that fill padding (zero-initialised, never written).
+__device__ __attribute__((aligned(16))) float kZeros[1024];
+__device__ __forceinline__ const float *zeros_for(int s) { return kZeros + ((s & 255) << 2); }
 
 // Wait until at most N vector-memory operations of this wave are pending and
 // its LDS operations are complete, then join the workgroup barrier.
@@ -109,40 +116,26 @@ struct SKc {
     }
     int64_t gr = r0 + r;
     if (gr >= rows) gr = rows - 1;
-    int gk = k0 + k;
-    if (gk >= kend) gk = 0;
+    const int gk = k0 + k;
+    if (gk >= kend) return zeros_for(s);
     return p + gr * ld + gk;
   }
   template <int BR>
-  __device__ bf16x8 frag(const char *lds, int rg, int q16, int g4, int64_t, int k0, int kend, bool tail) const {
+  __device__ void init_lds(char *, int, int, int64_t, int) const {}
+  template <int BR>
+  __device__ bf16x8 frag(const char *lds, int rg, int q16, int g4) const {
     const int r = rg * 16 + q16;
     const float *row = reinterpret_cast<const float *>(lds) + r * SBK;
-    floatx4 lo = *reinterpret_cast<const floatx4 *>(row + (((2 * g4) ^ (r & 7)) << 2));
-    floatx4 hi = *reinterpret_cast<const floatx4 *>(row + (((2 * g4 + 1) ^ (r & 7)) << 2));
-    if (tail) {
-      const int kb = k0 + 8 * g4;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (kb + e >= kend) lo[e] = 0.0f;
-        if (kb + 4 + e >= kend) hi[e] = 0.0f;
-      }
-    }
+    const floatx4 lo = *reinterpret_cast<const floatx4 *>(row + (((2 * g4) ^ (r & 7)) << 2));
+    const floatx4 hi = *reinterpret_cast<const floatx4 *>(row + (((2 * g4 + 1) ^ (r & 7)) << 2));
     return to_bf16x8(lo, hi);
   }
   // float32 values k = 16 h + 4 g4 .. + 3 of the stage for row rg*16 + q16
   template <int BR>
-  __device__ floatx4 frag4(const char *lds, int rg, int q16, int g4, int64_t, int k0, int kend, bool tail,
-                           int h) const {
+  __device__ floatx4 frag4(const char *lds, int rg, int q16, int g4, int h) const {
     const int r = rg * 16 + q16;
     const float *row = reinterpret_cast<const float *>(lds) + r * SBK;
-    floatx4 v = *reinterpret_cast<const floatx4 *>(row + (((4 * h + g4) ^ (r & 7)) << 2));
-    if (tail) {
-      const int kb = k0 + 16 * h + 4 * g4;
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (kb + e >= kend) v[e] = 0.0f;
-    }
-    return v;
+    return *reinterpret_cast<const floatx4 *>(row + (((4 * h + g4) ^ (r & 7)) << 2));
   }
 };
 
@@ -177,14 +170,27 @@ struct SRc {
       r = s - k * BR - 16 * hk(k);
       if (r < 0) r += BR;
     }
-    int64_t gr = r0 + r;
-    if (gr >= rows) gr = 0;
-    int gk = k0 + k;
-    if (gk >= kend) gk = kend - 1;
-    return p + (int64_t)gk * ld + gr;
+    const int64_t gr = r0 + r;
+    if (k0 + k >= kend) return zeros_for(s);
+    if (gr == ones) return nullptr;  // preset in LDS by init_lds
+    return p + (int64_t)(k0 + k) * ld + (gr >= rows ? 0 : gr);
+  }
+  // Write the ones row (and, for 16-byte lanes, zeros in the rest of its
+  // chunk, rows never stored) into all ns ring slots; stride: slot bytes.
+  template <int BR>
+  __device__ void init_lds(char *base, int ns, int stride, int64_t r0, int tid) const {
+    const int64_t ro = ones - r0;
+    if (ones < 0 || ro < 0 || ro >= BR) return;
+    const int slot = tid >> 5, k = tid & 31;
+    if (slot >= ns) return;
+    float *t = reinterpret_cast<float *>(base + slot * stride);
+    const int pos = ((int)ro + 16 * hk(k)) % BR;
+    t[k * BR + pos] = 1.0f;
+    if constexpr (VEC)
+      for (int q = 1; q < 4; ++q) t[k * BR + pos + q] = 0.0f;
   }
   template <int BR>
-  __device__ bf16x8 frag(const char *lds, int rg, int q16, int g4, int64_t r0, int k0, int kend, bool tail) const {
+  __device__ bf16x8 frag(const char *lds, int rg, int q16, int g4) const {
     constexpr int NG = BR / 16;
     const float *t = reinterpret_cast<const float *>(lds);
     // h(8 g4 + e) = (e >> 2) ^ (g4 & 1): position group rg + h (mod NG)
@@ -196,27 +202,10 @@ struct SRc {
       lo[e] = t[(8 * g4 + e) * BR + glo * 16 + q16];
       hi[e] = t[(8 * g4 + 4 + e) * BR + ghi * 16 + q16];
     }
-    const int kb = k0 + 8 * g4;
-    if (tail) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (kb + e >= kend) lo[e] = 0.0f;
-        if (kb + 4 + e >= kend) hi[e] = 0.0f;
-      }
-    }
-    const int64_t rbase = r0 + rg * 16;
-    if (ones >= rbase && ones < rbase + 16 && rbase + q16 == ones) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        lo[e] = kb + e < kend ? 1.0f : 0.0f;
-        hi[e] = kb + 4 + e < kend ? 1.0f : 0.0f;
-      }
-    }
     return to_bf16x8(lo, hi);
   }
   template <int BR>
-  __device__ floatx4 frag4(const char *lds, int rg, int q16, int g4, int64_t r0, int k0, int kend, bool tail,
-                           int h) const {
+  __device__ floatx4 frag4(const char *lds, int rg, int q16, int g4, int h) const {
     constexpr int NG = BR / 16;
     const float *t = reinterpret_cast<const float *>(lds);
     // k = 16 h + 4 g4 + j: h(k) = (g4 ^ (g4 >> 1)) & 1 for every j
@@ -225,17 +214,6 @@ struct SRc {
     floatx4 v;
 #pragma unroll
     for (int j = 0; j < 4; ++j) v[j] = t[(16 * h + 4 * g4 + j) * BR + pg * 16 + q16];
-    const int kb = k0 + 16 * h + 4 * g4;
-    if (tail) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (kb + j >= kend) v[j] = 0.0f;
-    }
-    const int64_t rbase = r0 + rg * 16;
-    if (ones >= rbase && ones < rbase + 16 && rbase + q16 == ones) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) v[j] = kb + j < kend ? 1.0f : 0.0f;
-    }
     return v;
   }
 };
@@ -252,6 +230,8 @@ struct SKh {
   template <int BR>
   static constexpr int slots() { return bytes<BR>() / kUnit; }
   template <int BR>
+  __device__ void init_lds(char *, int, int, int64_t, int) const {}
+  template <int BR>
   __device__ const uint16_t *src(int s, int64_t r0, int k0, int) const {
     const int r = s >> 2, c = (s & 3) ^ ((r >> 1) & 3);
     int64_t gr = r0 + r;
@@ -259,7 +239,7 @@ struct SKh {
     return p + gr * ldp + k0 + 8 * c;
   }
   template <int BR>
-  __device__ bf16x8 frag(const char *lds, int rg, int q16, int g4, int64_t, int, int, bool) const {
+  __device__ bf16x8 frag(const char *lds, int rg, int q16, int g4) const {
     const int r = rg * 16 + q16;
     return *reinterpret_cast<const bf16x8 *>(lds + r * 64 + ((g4 ^ ((r >> 1) & 3)) << 4));
   }
@@ -275,23 +255,19 @@ struct SCfg {
   static_assert(NS >= 2 && NS <= 4, "ring depth");
 };
 
-// One stage (32 k) of MFMAs for a consumer wave's TM x TN tiles.
+// One stage (32 k) of MFMAs for a wave's TM x TN tiles.
 template <class CF, bool F32, class AO, class BO>
 __device__ __forceinline__ void mma_stage(const AO &ao, const BO &bo, const char *sa, const char *sb, int wm, int wn,
-                                          int q16, int g4, int64_t m0, int n0, int k0, int kend,
-                                          floatx4 (&acc)[CF::TM][CF::TN]) {
+                                          int q16, int g4, floatx4 (&acc)[CF::TM][CF::TN]) {
   constexpr int BM = CF::BM, BN = CF::BN;
-  const bool tail = k0 + SBK > kend;
   if constexpr (F32) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       floatx4 a[CF::TM], b[CF::TN];
 #pragma unroll
-      for (int i = 0; i < CF::TM; ++i)
-        a[i] = ao.template frag4<BM>(sa, wm * CF::TM + i, q16, g4, m0, k0, kend, tail, h);
+      for (int i = 0; i < CF::TM; ++i) a[i] = ao.template frag4<BM>(sa, wm * CF::TM + i, q16, g4, h);
 #pragma unroll
-      for (int j = 0; j < CF::TN; ++j)
-        b[j] = bo.template frag4<BN>(sb, wn * CF::TN + j, q16, g4, n0, k0, kend, tail, h);
+      for (int j = 0; j < CF::TN; ++j) b[j] = bo.template frag4<BN>(sb, wn * CF::TN + j, q16, g4, h);
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj)
 #pragma unroll
@@ -303,9 +279,9 @@ __device__ __forceinline__ void mma_stage(const AO &ao, const BO &bo, const char
   } else {
     bf16x8 a[CF::TM], b[CF::TN];
 #pragma unroll
-    for (int i = 0; i < CF::TM; ++i) a[i] = ao.template frag<BM>(sa, wm * CF::TM + i, q16, g4, m0, k0, kend, tail);
+    for (int i = 0; i < CF::TM; ++i) a[i] = ao.template frag<BM>(sa, wm * CF::TM + i, q16, g4);
 #pragma unroll
-    for (int j = 0; j < CF::TN; ++j) b[j] = bo.template frag<BN>(sb, wn * CF::TN + j, q16, g4, n0, k0, kend, tail);
+    for (int j = 0; j < CF::TN; ++j) b[j] = bo.template frag<BN>(sb, wn * CF::TN + j, q16, g4);
 #pragma unroll
     for (int i = 0; i < CF::TM; ++i)
 #pragma unroll
@@ -394,7 +370,10 @@ __device__ __forceinline__ void dma_stage(const OPND &op, char *dst, int first, 
   for (int i = 0; i < (NI + step - 1) / step; ++i) {
     const int inst = first + step * i;
     const int s = inst * 64 + lane;
-    if (inst < NI && s < NSL) dma_to_lds<OPND::kUnit>(op.template src<BR>(s, r0, k0, kend), dst + inst * 64 * OPND::kUnit);
+    if (inst < NI && s < NSL) {
+      const void *src = op.template src<BR>(s, r0, k0, kend);
+      if (src) dma_to_lds<OPND::kUnit>(src, dst + inst * 64 * OPND::kUnit);
+    }
   }
 }
 
@@ -444,6 +423,8 @@ __global__ __launch_bounds__(256) void gemm_stream_kernel(AO ao, BO bo, CS cs, i
 #pragma unroll
     for (int j = 0; j < CF::TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+  ao.template init_lds<BM>(lds, NS, SB, m0, tid);
+  bo.template init_lds<BN>(lds + AB, NS, SB, n0, tid);
 #pragma unroll
   for (int s = 0; s < D; ++s)
     if (s < niter) issue(s);
@@ -461,7 +442,7 @@ __global__ __launch_bounds__(256) void gemm_stream_kernel(AO ao, BO bo, CS cs, i
     }
     if (it + D < niter) issue(it + D);
     const char *sa = lds + (it % NS) * SB;
-    mma_stage<CF, F32>(ao, bo, sa, sa + AB, wm, wn, q16, g4, m0, n0, kbeg + it * SBK, kend, acc);
+    mma_stage<CF, F32>(ao, bo, sa, sa + AB, wm, wn, q16, g4, acc);
   }
   store_tiles<CF>(cs, acc, M, N, m0, n0, wm, wn, q16, g4, z);
 }
@@ -519,6 +500,9 @@ struct CRowSide {
 using SCfgWide = SCfg<128, 96, 2, 2, 3>;    // N = 1440, 2880: 15 / 30 tiles exactly
 using SCfgNarrow = SCfg<128, 144, 4, 1, 3>; // 96 < N <= 144 (N = 135, 136)
 using SCfgSmall = SCfg<128, 48, 4, 1, 3>;   // N <= 96
+// weight gradient: two float32 operands per stage (34 KB); a two-stage ring
+// keeps two blocks per CU
+using SCfgGrad = SCfg<128, 144, 4, 1, 2>;
 
 template <int OP, bool F32, class AO, class BO, class CS>
 int stream_table_c(AO ao, BO bo, CS cs, const TableGemm &t, hipStream_t st) {
@@ -555,7 +539,7 @@ int stream_table_op(const TableGemm &t, hipStream_t st) {
 
 template <bool F32, class AO, class BO, class CS>
 int stream_grad(AO ao, BO bo, CS cs, int64_t rows, int cols, int64_t V, int splits, int ks, hipStream_t st) {
-  return run_stream<kOpFoldGrad, SCfgNarrow, F32>(ao, bo, cs, rows, cols, (int)V, splits, ks, st);
+  return run_stream<kOpFoldGrad, SCfgGrad, F32>(ao, bo, cs, rows, cols, (int)V, splits, ks, st);
 }
 
 }  // namespace streaming
