@@ -255,14 +255,16 @@ struct SCfg {
   static_assert(NS >= 2 && NS <= 4, "ring depth");
 };
 
-// One stage (32 k) of MFMAs for a wave's TM x TN tiles.
+// One stage (32 k) of MFMAs for a wave's TM x TN tiles.  FP32 runs the
+// stage's nh (1 or 2) groups of 16 k through one MFMA sequence (a last stage
+// ending within its first group needs one); BF16 ignores nh.
 template <class CF, bool F32, class AO, class BO>
 __device__ __forceinline__ void mma_stage(const AO &ao, const BO &bo, const char *sa, const char *sb, int wm, int wn,
-                                          int q16, int g4, floatx4 (&acc)[CF::TM][CF::TN]) {
+                                          int q16, int g4, int nh, floatx4 (&acc)[CF::TM][CF::TN]) {
   constexpr int BM = CF::BM, BN = CF::BN;
   if constexpr (F32) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
+#pragma unroll 1
+    for (int h = 0; h < nh; ++h) {
       floatx4 a[CF::TM], b[CF::TN];
 #pragma unroll
       for (int i = 0; i < CF::TM; ++i) a[i] = ao.template frag4<BM>(sa, wm * CF::TM + i, q16, g4, h);
@@ -428,7 +430,7 @@ __global__ __launch_bounds__(256) void gemm_stream_kernel(AO ao, BO bo, CS cs, i
 #pragma unroll
   for (int s = 0; s < D; ++s)
     if (s < niter) issue(s);
-  for (int it = 0; it < niter; ++it) {
+  auto wait_issue = [&](int it) {
     const int after = min(D - 1, niter - 1 - it);  // stages issued after this one
     if constexpr (D >= 3) {
       if (after >= 2) wait_barrier<2 * NIW>();
@@ -441,8 +443,12 @@ __global__ __launch_bounds__(256) void gemm_stream_kernel(AO ao, BO bo, CS cs, i
       wait_barrier<0>();
     }
     if (it + D < niter) issue(it + D);
+  };
+  for (int it = 0; it < niter; ++it) {
+    wait_issue(it);
     const char *sa = lds + (it % NS) * SB;
-    mma_stage<CF, F32>(ao, bo, sa, sa + AB, wm, wn, q16, g4, acc);
+    const int nh = kend - (kbeg + it * SBK) > 16 ? 2 : 1;
+    mma_stage<CF, F32>(ao, bo, sa, sa + AB, wm, wn, q16, g4, nh, acc);
   }
   store_tiles<CF>(cs, acc, M, N, m0, n0, wm, wn, q16, g4, z);
 }
