@@ -53,7 +53,6 @@ enum KernelOp : int {
   kOpFoldFwd,
   kOpFoldBwdData,
   kOpFoldGrad,
-  kOpFoldUnfold,
   kOpS2shRaw,
 };
 

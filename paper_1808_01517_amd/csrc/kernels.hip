@@ -884,21 +884,26 @@ int launch_sum_partials(const float *part, int splits, int64_t n, float *out, vo
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// dTw viewed per (o,c): row r = (o,c), column k = (kk,j) of the Ko x Ki block.
-struct AUnfold {
-  static constexpr bool kContig = true;
-  static constexpr bool kMask = false;
-  const float *dTw;
-  int C, Ki, Ko, N1;
-  __device__ float operator()(int64_t r, int k, int) const {
-    const int o = (int)r / C, c = (int)r - o * C;
-    const int kk = k / Ki, j = k - kk * Ki;
-    return dTw[((int64_t)o * Ko + kk) * N1 + (int64_t)c * Ki + j];
+// dW[(o*C+c)][t] = sum_{kk,j} dTw[(o*Ko+kk)][c*Ki+j] Q[t][kk][j]: one wave
+// per output (O*C*T of them), lanes striding the Ko*Ki-long reduction in a
+// fixed order, then a butterfly sum.  (A GEMM here has a 96 x 17 output and
+// a 2025-deep reduction: two blocks, all latency.)
+__global__ __launch_bounds__(256) void unfold_kernel(const float *dTw, const float *Q, int C, int T, int Ki, int Ko,
+                                                     int N1, int nout, float *dW) {
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (w >= nout) return;  // whole waves only
+  const int t = w % T, oc = w / T, o = oc / C, c = oc - o * C;
+  const int KK = Ko * Ki;
+  const float *q = Q + (int64_t)t * KK;
+  const float *g = dTw + (int64_t)o * Ko * N1 + (int64_t)c * Ki;
+  float s = 0.0f;
+  for (int e = lane; e < KK; e += 64) {
+    const int kk = e / Ki, j = e - kk * Ki;
+    s += g[(int64_t)kk * N1 + j] * q[e];
   }
-  __device__ floatx4 load4(int64_t r, int k, int g) const {
-    return floatx4{(*this)(r, k, g), (*this)(r, k + 1, g), (*this)(r, k + 2, g), (*this)(r, k + 3, g)};
-  }
-};
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) dW[(int64_t)oc * T + t] = s;
+}
 
 __global__ void bias_grad_kernel(const float *dTw, const float *pm1, int O, int Ko, int N1, int CK, float *db) {
   const int o = blockIdx.x * blockDim.x + threadIdx.x;
@@ -912,9 +917,11 @@ int launch_lsc_unfold(const float *dTw, const float *Q, const float *pm1, int C,
                       float *dW, float *db, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   const int N1 = C * Ki + 1;
-  int rc = run_gemm<kOpFoldUnfold>(AUnfold{dTw, C, Ki, Ko, N1}, BTableF{Q, 0, Ko * Ki}, CRowMajor{dW, T, 0, 0, nullptr},
-                                   (int64_t)O * C, T, Ko * Ki, 1, 0, DLM_FP32, st, pick_shape(T));
-  if (rc != 0 || !db) return rc;
+  const int nout = O * C * T;
+  hipLaunchKernelGGL(unfold_kernel, dim3((unsigned)((nout + 3) / 4)), dim3(256), 0, st, dTw, Q, C, T, Ki, Ko, N1, nout,
+                     dW);
+  if (hipGetLastError() != hipSuccess) return -1;
+  if (!db) return 0;
   hipLaunchKernelGGL(bias_grad_kernel, dim3((O + 63) / 64), dim3(64), 0, st, dTw, pm1, O, Ko, N1, C * Ki, db);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
