@@ -98,6 +98,13 @@ struct dlm_sh_plan {
   bool uniform = true;
   // device, all shells back to back: P [S][K][N], Pt [S][N][K], B [S][N][K], Bt [S][K][N]
   DevMat dP, dPt, dB, dBt;
+  // the same four tables in MFMA fragment order for the per-shell kernel
+  // (shell_frag_tables), all shells back to back; per-shell offsets in elements
+  float *fragF[4] = {nullptr, nullptr, nullptr, nullptr};
+  uint16_t *fragH[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<int64_t> frag_offF[4], frag_offH[4];
+  std::vector<float> stage_ff;
+  std::vector<uint16_t> stage_fh;
   int n_b0 = 0;
   int32_t *d_dwidx = nullptr;  // [n_dw] creation-table index of each shell-major volume
   int32_t *d_b0idx = nullptr;  // [n_b0] creation-table indices of the b=0 volumes
@@ -172,6 +179,47 @@ dlm_status sh_upload(dlm_sh_plan *p, hipStream_t st) {
     if (hipMemcpyAsync(d.f32, f, n * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(d.bf16, h, n * sizeof(uint16_t), hipMemcpyHostToDevice, st) != hipSuccess)
       return fail(DLM_EDEVICE, "table upload failed: %s", hipGetErrorString(hipGetLastError()));
+  }
+  // fragment-order copies: table t of shell s is [ncol][nred] = the
+  // per-shell slice of P, Pt, B, Bt
+  {
+    size_t nf = 0, nh = 0;
+    for (int t = 0; t < 4; ++t)
+      for (int s = 0; s < p->S; ++s) {
+        const int N = int(p->dirs[s]), K = p->K;
+        const int ncol = (t == 0 || t == 3) ? K : N, nred = (t == 0 || t == 3) ? N : K;
+        nf += shell_frag_floats(ncol, nred);
+        nh += shell_frag_halves(ncol, nred);
+      }
+    p->stage_ff.resize(nf);
+    p->stage_fh.resize(nh);
+    size_t of = 0, oh = 0;
+    for (int t = 0; t < 4; ++t) {
+      const size_t f0 = of, h0 = oh;
+      p->frag_offF[t].assign(p->S, 0);
+      p->frag_offH[t].assign(p->S, 0);
+      int64_t toff = 0;  // offset of shell s in the back-to-back table
+      for (int s = 0; s < p->S; ++s) {
+        const int N = int(p->dirs[s]), K = p->K;
+        const int ncol = (t == 0 || t == 3) ? K : N, nred = (t == 0 || t == 3) ? N : K;
+        p->frag_offF[t][s] = int64_t(of - f0);
+        p->frag_offH[t][s] = int64_t(oh - h0);
+        shell_frag_tables(src[t]->data() + toff, ncol, nred, p->stage_ff.data() + of, p->stage_fh.data() + oh);
+        of += shell_frag_floats(ncol, nred);
+        oh += shell_frag_halves(ncol, nred);
+        toff += int64_t(N) * K;
+      }
+      const size_t cf = of - f0, ch = oh - h0;
+      if (!p->fragF[t] && hipMalloc(&p->fragF[t], cf * sizeof(float)) != hipSuccess)
+        return fail(DLM_ENOMEM, "hipMalloc failed");
+      if (!p->fragH[t] && hipMalloc(&p->fragH[t], ch * sizeof(uint16_t)) != hipSuccess)
+        return fail(DLM_ENOMEM, "hipMalloc failed");
+      if (hipMemcpyAsync(p->fragF[t], p->stage_ff.data() + f0, cf * sizeof(float), hipMemcpyHostToDevice, st) !=
+              hipSuccess ||
+          hipMemcpyAsync(p->fragH[t], p->stage_fh.data() + h0, ch * sizeof(uint16_t), hipMemcpyHostToDevice, st) !=
+              hipSuccess)
+        return fail(DLM_EDEVICE, "table upload failed: %s", hipGetErrorString(hipGetLastError()));
+    }
   }
   if (!p->staged && hipEventCreateWithFlags(&p->staged, hipEventDisableTiming) != hipSuccess)
     return fail(DLM_EDEVICE, "hipEventCreate failed");
@@ -350,6 +398,10 @@ void dlm_sh_plan_destroy(dlm_sh_plan *p) {
   }
   release(p->dP);
   release(p->dPt);
+  for (int t = 0; t < 4; ++t) {
+    if (p->fragF[t]) (void)hipFree(p->fragF[t]);
+    if (p->fragH[t]) (void)hipFree(p->fragH[t]);
+  }
   release(p->dB);
   release(p->dBt);
   if (p->d_dwidx) (void)hipFree(p->d_dwidx);
@@ -409,8 +461,34 @@ dlm_status sh_apply(const dlm_sh_plan *p, const float *in, float *out, int64_t V
     t.op = kops[int(op)];
     const double ng = double(t.groups);
     TimedScope ts(tags[int(op)], stream, double(V) * ng * (double(N) + K) * 4.0, 2.0 * double(V) * ng * N * K);
-    if (launch_table_gemm(t, prec, stream) != 0)
-      return fail(DLM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
+    int rc;
+    // one wave per 16 voxels x shell (tables in fragment order) for the
+    // contractions over the coefficients (K <= 64: Signal2SH adjoint,
+    // SH2Signal); reductions over a shell's directions keep the tiled core,
+    // which measured faster for them
+    if (shell_gemm_ok(t.N, t.K) && t.K <= 64) {
+      const int ti = int(op);
+      ShellGemm g;
+      g.A = t.A;
+      g.lda = t.lda;
+      g.a_gs = t.a_gs;
+      g.C = t.C;
+      g.ldc = t.ldc;
+      g.c_gs = t.c_gs;
+      g.frag_f = p->fragF[ti] + p->frag_offF[ti][s0];
+      g.frag_h = p->fragH[ti] + p->frag_offH[ti][s0];
+      g.frag_gs_f = int64_t(shell_frag_floats(t.N, t.K) * sizeof(float));
+      g.frag_gs_h = int64_t(shell_frag_halves(t.N, t.K) * sizeof(uint16_t));
+      g.ncol = t.N;
+      g.nred = t.K;
+      g.groups = t.groups;
+      g.V = V;
+      g.op = t.op;
+      rc = launch_shell_gemm(g, prec, stream);
+    } else {
+      rc = launch_table_gemm(t, prec, stream);
+    }
+    if (rc != 0) return fail(DLM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
   }
   return ok();
 }

@@ -89,6 +89,29 @@ int launch_stream_table(const TableGemm &g, dlm_precision prec, void *stream);
 // Weight-gradient form of launch_lsc_fold_grad (no mask), ksplit a multiple of 32.
 int launch_stream_grad(const float *g, const float *a, int64_t V, int M, int CK, int splits, int ksplit,
                        float *partial, dlm_precision prec, void *stream);
+// Per-shell SH contraction, one wave per 16 voxels x one shell (groups
+// shells of equal size in one launch):
+//   C[v][g*c_gs + n] = sum_k A[v][g*a_gs + k] * Bt_g[n][k],  n < ncol, k < nred
+// with Bt_g given in MFMA fragment order (shell_frag_tables), frag_gs_* the
+// per-shell stride of the fragment tables in bytes.  nred <= 128.
+struct ShellGemm {
+  const float *A = nullptr;
+  int64_t lda = 0, a_gs = 0;
+  float *C = nullptr;
+  int64_t ldc = 0, c_gs = 0;
+  const float *frag_f = nullptr;
+  const uint16_t *frag_h = nullptr;
+  int64_t frag_gs_f = 0, frag_gs_h = 0;
+  int ncol = 0, nred = 0, groups = 1;
+  int64_t V = 0;
+  KernelOp op = kOpS2shFwd;
+};
+bool shell_gemm_ok(int ncol, int nred);
+int launch_shell_gemm(const ShellGemm &g, dlm_precision prec, void *stream);
+size_t shell_frag_floats(int ncol, int nred);
+size_t shell_frag_halves(int ncol, int nred);
+void shell_frag_tables(const double *t, int ncol, int nred, float *f, uint16_t *h);
+
 // fill `bytes` (a multiple of 4) at p with zeros
 int launch_zero(void *p, size_t bytes, void *stream);
 

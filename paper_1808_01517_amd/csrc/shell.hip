@@ -1,0 +1,200 @@
+// Per-shell SH contractions (Sec. 2.2: Signal2SH c = P_s x, SH2Signal
+// x = B_s c, and their adjoints) for one MI355X.
+//
+// Each is, per voxel v and shell g,
+//   C[v][g*c_gs + n] = sum_k A[v][g*a_gs + k] * Bt_g[n][k],   n < ncol, k < nred,
+// with ncol, nred <= 96 for the workloads here (K = 45 coefficients, 90
+// directions per shell).  Such a contraction is a stream: 15 flop per byte
+// against a bf16 ridge near 300, so the design keeps the loads flowing and
+// nothing else in the way:
+// * one wave computes 16 voxels x one shell; its A fragments are loaded
+//   straight from HBM into registers (16-byte loads along the voxel's row,
+//   all issued before the first MFMA), so there is no LDS staging and no
+//   barrier, and many resident waves hide the latency;
+// * the table Bt_g arrives pre-arranged on the host in MFMA fragment order,
+//   one 16-byte load per lane per fragment (it stays in L1/L2);
+// * BF16: v_mfma_f32_16x16x32_bf16, lane (q16, g4) holds k = 32 s + 8 g4 .. + 7;
+//   FP32: v_mfma_f32_16x16x4_f32 over 16-k groups, lane (q16, g4) holds
+//   k = 16 h + 4 g4 .. + 3 and MFMA e takes k = 16 h + 4 g4 + e;
+// * the B fragment goes first, so each accumulator is the transposed 16 x 16
+//   tile and a lane stores four consecutive columns of one voxel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "gemm_common.h"
+#include "internal.h"
+
+namespace dlm {
+namespace shellk {
+
+constexpr int kMaxRed = 128;  // reduction length handled (FP32: 8 groups of 16, BF16: 4 steps of 32)
+constexpr int kColChunk = 6;  // output tiles of 16 per pass over A (96 columns)
+
+// 4 consecutive floats of row a from k, zero where k + e >= kend or the row is absent
+__device__ __forceinline__ floatx4 load_run(const float *a, int k, int kend, bool row) {
+  if (row && k + 3 < kend) return ld4(a + k);
+  floatx4 v{0.f, 0.f, 0.f, 0.f};
+  if (row)
+    for (int e = 0; e < 4; ++e)
+      if (k + e < kend) v[e] = a[k + e];
+  return v;
+}
+
+template <int OP, bool F32>
+__global__ __launch_bounds__(256) void shell_gemm_kernel(const float *A, int64_t lda, int64_t a_gs, float *C,
+                                                         int64_t ldc, int64_t c_gs, const void *frag,
+                                                         int64_t frag_gs, int ncol, int nred, int groups, int64_t V,
+                                                         int64_t nwaves) {
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= nwaves) return;  // whole waves only; no barriers in this kernel
+  const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
+  const int64_t rb = w / groups;
+  const int g = (int)(w - rb * groups);
+  const int64_t r = rb * 16 + q16;
+  const bool row = r < V;
+  const float *a = A + r * lda + (int64_t)g * a_gs;
+  float *c = C + r * ldc + (int64_t)g * c_gs;
+  const int NT = (ncol + 15) / 16;
+  if constexpr (F32) {
+    constexpr int HM = kMaxRed / 16;
+    const int H = (nred + 15) / 16;
+    const floatx4 *fr = reinterpret_cast<const floatx4 *>(frag) + (int64_t)g * frag_gs / 16;
+    floatx4 av[HM];
+#pragma unroll
+    for (int h = 0; h < HM; ++h) av[h] = h < H ? load_run(a, 16 * h + 4 * g4, nred, row) : floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int j0 = 0; j0 < NT; j0 += kColChunk) {
+      const int nt = min(kColChunk, NT - j0);
+      floatx4 acc[kColChunk];
+#pragma unroll
+      for (int j = 0; j < kColChunk; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int h = 0; h < HM; ++h) {
+        if (h >= H) break;
+#pragma unroll
+        for (int j = 0; j < kColChunk; ++j) {
+          if (j >= nt) break;
+          const floatx4 b = fr[((int64_t)(j0 + j) * H + h) * 64 + lane];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[e], av[h][e], acc[j], 0, 0, 0);
+        }
+      }
+      if (row) {
+#pragma unroll
+        for (int j = 0; j < kColChunk; ++j) {
+          if (j >= nt) break;
+          const int n = 16 * (j0 + j) + 4 * g4;
+          if (n + 3 < ncol) __builtin_memcpy(c + n, &acc[j], 16);
+          else
+            for (int e = 0; e < 4; ++e)
+              if (n + e < ncol) c[n + e] = acc[j][e];
+        }
+      }
+    }
+  } else {
+    constexpr int SM = kMaxRed / 32;
+    const int S = (nred + 31) / 32;
+    const bf16x8 *fr = reinterpret_cast<const bf16x8 *>(frag) + (int64_t)g * frag_gs / 16;
+    floatx4 lo[SM], hi[SM];
+#pragma unroll
+    for (int s = 0; s < SM; ++s) {
+      lo[s] = s < S ? load_run(a, 32 * s + 8 * g4, nred, row) : floatx4{0.f, 0.f, 0.f, 0.f};
+      hi[s] = s < S ? load_run(a, 32 * s + 8 * g4 + 4, nred, row) : floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    bf16x8 av[SM];
+#pragma unroll
+    for (int s = 0; s < SM; ++s)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        av[s][e] = (__bf16)lo[s][e];
+        av[s][4 + e] = (__bf16)hi[s][e];
+      }
+    for (int j0 = 0; j0 < NT; j0 += kColChunk) {
+      const int nt = min(kColChunk, NT - j0);
+      floatx4 acc[kColChunk];
+#pragma unroll
+      for (int j = 0; j < kColChunk; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < SM; ++s) {
+        if (s >= S) break;
+#pragma unroll
+        for (int j = 0; j < kColChunk; ++j) {
+          if (j >= nt) break;
+          const bf16x8 b = fr[((int64_t)(j0 + j) * S + s) * 64 + lane];
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, av[s], acc[j], 0, 0, 0);
+        }
+      }
+      if (row) {
+#pragma unroll
+        for (int j = 0; j < kColChunk; ++j) {
+          if (j >= nt) break;
+          const int n = 16 * (j0 + j) + 4 * g4;
+          if (n + 3 < ncol) __builtin_memcpy(c + n, &acc[j], 16);
+          else
+            for (int e = 0; e < 4; ++e)
+              if (n + e < ncol) c[n + e] = acc[j][e];
+        }
+      }
+    }
+  }
+}
+
+template <int OP>
+int launch_op(const ShellGemm &t, dlm_precision prec, hipStream_t st) {
+  const int64_t nwaves = (t.V + 15) / 16 * t.groups;
+  const int64_t blocks = (nwaves + 3) / 4;
+  if (blocks > 0x7fffffff) return -4;
+  if (prec == DLM_BF16)
+    hipLaunchKernelGGL((shell_gemm_kernel<OP, false>), dim3((unsigned)blocks), dim3(256), 0, st, t.A, t.lda, t.a_gs,
+                       t.C, t.ldc, t.c_gs, (const void *)t.frag_h, t.frag_gs_h, t.ncol, t.nred, t.groups, t.V, nwaves);
+  else
+    hipLaunchKernelGGL((shell_gemm_kernel<OP, true>), dim3((unsigned)blocks), dim3(256), 0, st, t.A, t.lda, t.a_gs,
+                       t.C, t.ldc, t.c_gs, (const void *)t.frag_f, t.frag_gs_f, t.ncol, t.nred, t.groups, t.V, nwaves);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace shellk
+
+bool shell_gemm_ok(int ncol, int nred) { return ncol > 0 && nred > 0 && nred <= shellk::kMaxRed; }
+
+int launch_shell_gemm(const ShellGemm &t, dlm_precision prec, void *stream) {
+  if (!shell_gemm_ok(t.ncol, t.nred)) return -3;
+  if (t.V <= 0) return 0;
+  hipStream_t st = (hipStream_t)stream;
+  switch (t.op) {
+    case kOpS2shFwd: return shellk::launch_op<kOpS2shFwd>(t, prec, st);
+    case kOpS2shBwd: return shellk::launch_op<kOpS2shBwd>(t, prec, st);
+    case kOpSh2sFwd: return shellk::launch_op<kOpSh2sFwd>(t, prec, st);
+    case kOpSh2sBwd: return shellk::launch_op<kOpSh2sBwd>(t, prec, st);
+    default: return -3;
+  }
+}
+
+// Fragment order of a [ncol][nred] table: float32 entry ((j*H + h)*64 + lane)*4 + e
+// holds Bt[16 j + lane % 16][16 h + 4 (lane / 16) + e]; bfloat16 entry
+// ((j*S + s)*64 + lane)*8 + e holds Bt[16 j + lane % 16][32 s + 8 (lane / 16) + e];
+// zero outside the table.
+size_t shell_frag_floats(int ncol, int nred) { return size_t((ncol + 15) / 16) * ((nred + 15) / 16) * 256; }
+size_t shell_frag_halves(int ncol, int nred) { return size_t((ncol + 15) / 16) * ((nred + 31) / 32) * 512; }
+
+void shell_frag_tables(const double *t, int ncol, int nred, float *f, uint16_t *h) {
+  const int NT = (ncol + 15) / 16, H = (nred + 15) / 16, S = (nred + 31) / 32;
+  for (int j = 0; j < NT; ++j)
+    for (int lane = 0; lane < 64; ++lane) {
+      const int col = 16 * j + (lane & 15), g4 = lane >> 4;
+      for (int hh = 0; hh < H; ++hh)
+        for (int e = 0; e < 4; ++e) {
+          const int red = 16 * hh + 4 * g4 + e;
+          f[((size_t(j) * H + hh) * 64 + lane) * 4 + e] =
+              col < ncol && red < nred ? float(t[size_t(col) * nred + red]) : 0.0f;
+        }
+      for (int s = 0; s < S; ++s)
+        for (int e = 0; e < 8; ++e) {
+          const int red = 32 * s + 8 * g4 + e;
+          h[((size_t(j) * S + s) * 64 + lane) * 8 + e] =
+              col < ncol && red < nred ? f64_to_bf16_rne(t[size_t(col) * nred + red]) : uint16_t(0);
+        }
+    }
+}
+
+}  // namespace dlm
