@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--voxels", type=int, default=None, help="override the voxel count (default: the workload's)")
     ap.add_argument("--chunk", type=int, default=1 << 17, help="LSC voxels per workspace pass")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--unfused-head", action="store_true",
+                    help="run the loss head as SH2Signal, MSE and SH2Signal adjoint in three calls")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--with-copy-calibration", action="store_true",
@@ -267,8 +269,10 @@ def main():
     acts = [torch.empty((V, S, K), **f32)] + [torch.empty((V, ch[k + 1], p.K_out), **f32)
                                               for k, (p, _, _, _) in enumerate(layers)]
     grads = [torch.empty_like(a) for a in acts]
-    xhat = torch.empty_like(x)
-    dxhat = torch.empty_like(x)
+    fused_head = dl.sh2signal_mse_supported(plan) and not args.unfused_head
+    xhat = None if fused_head else torch.empty_like(x)
+    dxhat = None if fused_head else torch.empty_like(x)
+    head_ws = torch.empty(dl.lib().dlm_sh2signal_mse_workspace_bytes(plan.handle, V), dtype=torch.uint8, device=dev)
     dx = torch.empty_like(x)
     dWs = [torch.empty_like(Wk) for _, Wk, _, _ in layers]
     dbs = [torch.empty_like(bk) for _, _, bk, _ in layers]
@@ -283,9 +287,12 @@ def main():
         dl.signal2sh_fwd(plan, x, out=acts[0], precision=prec)
         for k, (p, Wk, bk, relu) in enumerate(layers):
             dl.lsc_fwd(p, acts[k], Wk, bk, relu=relu, out=acts[k + 1], precision=prec, workspace=ws, form=form)
-        dl.sh2signal_fwd(plan, acts[-1], out=xhat, precision=prec)
-        dl.mse_fwd_bwd(xhat, tgt, outs=(loss, dxhat, mse_ws))
-        dl.sh2signal_bwd(plan, dxhat, out=grads[-1], precision=prec)
+        if fused_head:  # x^ and its gradient never go through HBM
+            dl.sh2signal_mse_fwd_bwd(plan, acts[-1], tgt, precision=prec, outs=(loss, grads[-1], head_ws))
+        else:
+            dl.sh2signal_fwd(plan, acts[-1], out=xhat, precision=prec)
+            dl.mse_fwd_bwd(xhat, tgt, outs=(loss, dxhat, mse_ws))
+            dl.sh2signal_bwd(plan, dxhat, out=grads[-1], precision=prec)
         for k in range(len(layers) - 1, -1, -1):
             p, Wk, bk, relu = layers[k]
             # the ReLU after layer k-1 is applied by layer k's adjoint as it writes grads[k]
@@ -321,7 +328,8 @@ def main():
         "config": {"workload": w.name, "voxels": V, "shells": len(w.shell_b), "dirs_per_shell": w.dirs_per_shell,
                    "b0_volumes": w.n_b0, "sh_order": w.sh_order, "lsc_channels": list(ch),
                    "kernel_sizes": list(w.kernel_sizes), "angular_distance_deg": 30.0, "lsc_form": form,
-                   "precision": prec, "lsc_chunk_voxels": min(V, args.chunk)},
+                   "precision": prec, "lsc_chunk_voxels": min(V, args.chunk),
+                   "loss_head": "fused" if fused_head else "unfused"},
     }
 
     if not args.no_kernel_timing:

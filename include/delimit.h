@@ -120,6 +120,26 @@ dlm_status dlm_sh2signal_fwd(const dlm_sh_plan *plan, const float *c, float *x, 
 dlm_status dlm_sh2signal_bwd(const dlm_sh_plan *plan, const float *dx, float *dc, int64_t V,
                              dlm_precision prec, void *stream);
 
+/* The q-space loss head of training (Sec. 1: the network's SH output is
+ * taken back to q-space by SH2Signal, Sec. 2.2, and compared there), fused
+ * into one pass so that neither the predicted signal nor its gradient has
+ * to go through device memory:
+ *   xhat[v][s-block] = B_s c[v][s][:]
+ *   loss             = mean over V * N_dw of (xhat - target)^2   (device scalar)
+ *   dc[v][s][:]      = B_s^T (2 (xhat - target) / (V N_dw))[v][s-block]
+ * c device [V][S][K]; target, xhat device [V][N_dw] (xhat may be NULL, then
+ * it is not written); dc device [V][S][K] (must not alias c).  Same result as
+ * dlm_sh2signal_fwd, dlm_mse_fwd_bwd and dlm_sh2signal_bwd in a row.
+ * Supported when every shell has at most 96 directions and K <= 64 (sh
+ * order <= 8); dlm_sh2signal_mse_supported says whether a plan qualifies,
+ * otherwise the call returns DLM_EINVAL.  ws: device workspace of at least
+ * dlm_sh2signal_mse_workspace_bytes(plan, V) bytes (per-wave partial sums). */
+int dlm_sh2signal_mse_supported(const dlm_sh_plan *plan);
+size_t dlm_sh2signal_mse_workspace_bytes(const dlm_sh_plan *plan, int64_t V);
+dlm_status dlm_sh2signal_mse_fwd_bwd(const dlm_sh_plan *plan, const float *c, const float *target, int64_t V,
+                                     float *loss, float *dc, float *xhat, void *ws, size_t ws_bytes,
+                                     dlm_precision prec, void *stream);
+
 /* Signal2SH straight from raw acquisitions, with the b=0 normalisation the
  * layer requires of its input (Sec. 2.2) fused into the load:
  *   c[v][s][:] = P_s (raw[v][dw volumes of shell s] / mean_b0(raw[v]))

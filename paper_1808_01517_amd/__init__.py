@@ -22,7 +22,8 @@ __all__ = [
     "SHPlan", "LSCPlan", "precision_code", "signal2sh_fwd", "signal2sh_bwd", "sh2signal_fwd", "sh2signal_bwd",
     "lsc_fwd", "lsc_bwd", "lsc_workspace_bytes", "mse_fwd_bwd", "adam_step", "Workspace", "DelimitError",
     "sh_basis", "sh_fit_matrix", "lsc_kernel_points", "timing_enable", "timing_reset", "timing_report",
-    "form_code", "DEFAULT_FORM", "signal2sh_fwd_raw", "relmse_fwd_bwd",
+    "form_code", "DEFAULT_FORM", "signal2sh_fwd_raw", "relmse_fwd_bwd", "sh2signal_mse_supported",
+    "sh2signal_mse_fwd_bwd",
 ]
 
 
@@ -338,6 +339,43 @@ def mse_fwd_bwd(pred: torch.Tensor, target: torch.Tensor, need_grad: bool = True
     check(lib().dlm_mse_fwd_bwd(_ptr(pred), _ptr(target), n, _ptr(loss), _ptr(dpred), _ptr(ws), ws.numel(),
                                 _stream(pred)))
     return loss, dpred
+
+
+def sh2signal_mse_supported(plan: SHPlan) -> bool:
+    """Whether the fused loss head takes this plan (<= 96 directions per
+    shell, K <= 64)."""
+    return bool(lib().dlm_sh2signal_mse_supported(plan.handle))
+
+
+def sh2signal_mse_fwd_bwd(plan: SHPlan, c: torch.Tensor, target: torch.Tensor, need_xhat: bool = False,
+                          precision="fp32", outs=None, xhat_out=None):
+    """The q-space loss head in one pass: (loss device scalar, dc [V][S][K],
+    xhat [V][N_dw] or None) for xhat = SH2Signal(c) and loss =
+    mean((xhat - target)^2), dc its gradient.  `outs` = (loss, dc, workspace)
+    preallocated tensors; `xhat_out` a preallocated xhat (implies need_xhat)."""
+    c = _f32_dev(c, "c")
+    target = _f32_dev(target, "target")
+    if c.dim() != 3 or tuple(c.shape[1:]) != (plan.n_shells, plan.K):
+        raise ValueError(f"c must be [V, {plan.n_shells}, {plan.K}]")
+    V = c.shape[0]
+    if tuple(target.shape) != (V, plan.n_dw):
+        raise ValueError(f"target must be [{V}, {plan.n_dw}]")
+    if outs is not None:
+        loss, dc, ws = outs
+    else:
+        ws = torch.empty(lib().dlm_sh2signal_mse_workspace_bytes(plan.handle, V), dtype=torch.uint8,
+                         device=c.device)
+        loss = torch.empty((), dtype=torch.float32, device=c.device)
+        dc = torch.empty_like(c)
+    xhat = xhat_out
+    if xhat is not None:
+        if tuple(xhat.shape) != (V, plan.n_dw) or xhat.dtype != torch.float32 or not xhat.is_contiguous():
+            raise ValueError(f"xhat_out must be a contiguous float32 [{V}, {plan.n_dw}] tensor")
+    elif need_xhat:
+        xhat = torch.empty((V, plan.n_dw), dtype=torch.float32, device=c.device)
+    check(lib().dlm_sh2signal_mse_fwd_bwd(plan.handle, _ptr(c), _ptr(target), V, _ptr(loss), _ptr(dc), _ptr(xhat),
+                                          _ptr(ws), ws.numel(), precision_code(precision), _stream(c)))
+    return loss, dc, xhat
 
 
 def relmse_fwd_bwd(pred: torch.Tensor, target: torch.Tensor, eps: float = 1e-3, need_grad: bool = True):

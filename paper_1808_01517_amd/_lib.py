@@ -51,6 +51,9 @@ SIGNATURES = {
     "dlm_signal2sh_raw_workspace_bytes": (C.c_size_t, [_i64]),
     "dlm_signal2sh_fwd_raw": (_st, [_p, _p, _p, _i64, _p, C.c_size_t, _int, _p]),
     "dlm_relmse_fwd_bwd": (_st, [_p, _p, _i64, C.c_float, _p, _p, _p, C.c_size_t, _p]),
+    "dlm_sh2signal_mse_supported": (_int, [_p]),
+    "dlm_sh2signal_mse_workspace_bytes": (C.c_size_t, [_p, _i64]),
+    "dlm_sh2signal_mse_fwd_bwd": (_st, [_p, _p, _p, _i64, _p, _p, _p, _p, C.c_size_t, _int, _p]),
     "dlm_timing_enable": (_st, [_int]),
     "dlm_timing_reset": (_st, []),
     "dlm_timing_count": (_int, []),

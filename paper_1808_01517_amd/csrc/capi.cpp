@@ -103,8 +103,11 @@ struct dlm_sh_plan {
   float *fragF[4] = {nullptr, nullptr, nullptr, nullptr};
   uint16_t *fragH[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<int64_t> frag_offF[4], frag_offH[4];
+  // Bt in the accumulator order of the fused loss head (shell_frag_halves_acc),
+  // same offsets as frag_offH[3]
+  uint16_t *fragHacc = nullptr;
   std::vector<float> stage_ff;
-  std::vector<uint16_t> stage_fh;
+  std::vector<uint16_t> stage_fh, stage_hacc;
   int n_b0 = 0;
   int32_t *d_dwidx = nullptr;  // [n_dw] creation-table index of each shell-major volume
   int32_t *d_b0idx = nullptr;  // [n_b0] creation-table indices of the b=0 volumes
@@ -220,6 +223,22 @@ dlm_status sh_upload(dlm_sh_plan *p, hipStream_t st) {
               hipSuccess)
         return fail(DLM_EDEVICE, "table upload failed: %s", hipGetErrorString(hipGetLastError()));
     }
+    size_t na = 0;
+    for (int s = 0; s < p->S; ++s) na += shell_frag_halves(p->K, int(p->dirs[s]));
+    p->stage_hacc.resize(na);
+    size_t oa = 0;
+    int64_t toff = 0;
+    for (int s = 0; s < p->S; ++s) {
+      const int N = int(p->dirs[s]), K = p->K;
+      shell_frag_halves_acc(Bt.data() + toff, K, N, p->stage_hacc.data() + oa);
+      oa += shell_frag_halves(K, N);
+      toff += int64_t(N) * K;
+    }
+    if (!p->fragHacc && hipMalloc(&p->fragHacc, na * sizeof(uint16_t)) != hipSuccess)
+      return fail(DLM_ENOMEM, "hipMalloc failed");
+    if (hipMemcpyAsync(p->fragHacc, p->stage_hacc.data(), na * sizeof(uint16_t), hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+      return fail(DLM_EDEVICE, "table upload failed: %s", hipGetErrorString(hipGetLastError()));
   }
   if (!p->staged && hipEventCreateWithFlags(&p->staged, hipEventDisableTiming) != hipSuccess)
     return fail(DLM_EDEVICE, "hipEventCreate failed");
@@ -402,6 +421,7 @@ void dlm_sh_plan_destroy(dlm_sh_plan *p) {
     if (p->fragF[t]) (void)hipFree(p->fragF[t]);
     if (p->fragH[t]) (void)hipFree(p->fragH[t]);
   }
+  if (p->fragHacc) (void)hipFree(p->fragHacc);
   release(p->dB);
   release(p->dBt);
   if (p->d_dwidx) (void)hipFree(p->d_dwidx);
@@ -539,6 +559,79 @@ dlm_status dlm_sh2signal_fwd(const dlm_sh_plan *p, const float *c, float *x, int
 }
 dlm_status dlm_sh2signal_bwd(const dlm_sh_plan *p, const float *dx, float *dc, int64_t V, dlm_precision prec, void *st) {
   return sh_apply(p, dx, dc, V, prec, st, ShOp::Sh2sBwd);
+}
+
+int dlm_sh2signal_mse_supported(const dlm_sh_plan *p) {
+  if (!p) return 0;
+  for (int s = 0; s < p->S; ++s)
+    if (!sh2s_mse_ok(int(p->dirs[s]), p->K)) return 0;
+  return 1;
+}
+
+namespace {
+int64_t sh2s_mse_waves(const dlm_sh_plan *p, int64_t V) {
+  return p->uniform ? sh2s_mse_partials(V, p->S) : sh2s_mse_partials(V, 1) * p->S;
+}
+}  // namespace
+
+size_t dlm_sh2signal_mse_workspace_bytes(const dlm_sh_plan *p, int64_t V) {
+  if (!p) return 0;
+  return align256(size_t(sh2s_mse_waves(p, std::max<int64_t>(V, 1))) * 4);
+}
+
+dlm_status dlm_sh2signal_mse_fwd_bwd(const dlm_sh_plan *p, const float *c, const float *target, int64_t V,
+                                     float *loss, float *dc, float *xhat, void *ws, size_t ws_bytes,
+                                     dlm_precision prec, void *stream) {
+  if (!p) return fail(DLM_EINVAL, "plan is NULL");
+  if (V <= 0) return fail(DLM_EINVAL, "V must be > 0");
+  if (prec != DLM_FP32 && prec != DLM_BF16) return fail(DLM_EINVAL, "unknown precision %d", int(prec));
+  if (!dlm_sh2signal_mse_supported(p))
+    return fail(DLM_EINVAL, "fused loss head needs <= 96 directions per shell and K <= 64");
+  if (!c || !target || !loss || !dc || !ws) return fail(DLM_EINVAL, "null device pointer");
+  if (dc == c) return fail(DLM_EINVAL, "dc must not alias c");
+  if (ws_bytes < dlm_sh2signal_mse_workspace_bytes(p, V)) return fail(DLM_EWORKSPACE, "workspace too small");
+  const int K = p->K, S = p->S;
+  const int64_t ndw = p->n_dw;
+  const double numel = double(V) * double(ndw);
+  float *partials = static_cast<float *>(ws);
+  const int shells = p->uniform ? 1 : S;
+  int64_t pw = 0;
+  for (int s0 = 0; s0 < shells; ++s0) {
+    const int N = int(p->dirs[s0]);
+    Sh2sMse t;
+    t.groups = p->uniform ? S : 1;
+    const int64_t sig_off = p->uniform ? 0 : p->offs[s0];
+    const int64_t coef_off = p->uniform ? 0 : int64_t(s0) * K;
+    t.c = c + coef_off;
+    t.dc = dc + coef_off;
+    t.ldcoef = int64_t(S) * K;
+    t.K = K;
+    t.target = target + sig_off;
+    t.xhat = xhat ? xhat + sig_off : nullptr;
+    t.ldsig = ndw;
+    t.N = N;
+    // B is table 2 ([N][K]), B^T table 3 ([K][N])
+    t.fragB_f = p->fragF[2] + p->frag_offF[2][s0];
+    t.fragB_h = p->fragH[2] + p->frag_offH[2][s0];
+    t.fragBt_f = p->fragF[3] + p->frag_offF[3][s0];
+    t.fragBt_h = p->fragHacc + p->frag_offH[3][s0];
+    t.gsB_f = int64_t(shell_frag_floats(N, K) * sizeof(float));
+    t.gsB_h = int64_t(shell_frag_halves(N, K) * sizeof(uint16_t));
+    t.gsBt_f = int64_t(shell_frag_floats(K, N) * sizeof(float));
+    t.gsBt_h = int64_t(shell_frag_halves(K, N) * sizeof(uint16_t));
+    t.V = V;
+    t.scale = float(2.0 / numel);
+    t.partials = partials + pw;
+    pw += sh2s_mse_partials(V, t.groups);
+    const double ng = double(t.groups);
+    TimedScope ts("sh2signal_mse", stream, double(V) * ng * (2.0 * K + N * (xhat ? 2.0 : 1.0)) * 4.0,
+                  4.0 * double(V) * ng * N * K);
+    if (launch_sh2s_mse(t, prec, stream) != 0)
+      return fail(DLM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
+  }
+  if (launch_sum_partials(partials, pw, loss, float(1.0 / numel), stream) != 0)
+    return fail(DLM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
+  return ok();
 }
 
 // ----------------------------------------------------------------- LSC plan

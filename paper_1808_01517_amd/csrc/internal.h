@@ -111,6 +111,38 @@ int launch_shell_gemm(const ShellGemm &g, dlm_precision prec, void *stream);
 size_t shell_frag_floats(int ncol, int nred);
 size_t shell_frag_halves(int ncol, int nred);
 void shell_frag_tables(const double *t, int ncol, int nred, float *f, uint16_t *h);
+// bf16 fragment table of Bt [ncol][nred] with the reduction index in the
+// accumulator order of sh2s_mse_kernel's second contraction
+void shell_frag_halves_acc(const double *t, int ncol, int nred, uint16_t *h);
+
+// Fused SH2Signal -> MSE -> SH2Signal adjoint over `groups` shells of N
+// directions each (c [V][ldcoef], shell g at g*K; target/xhat [V][ldsig],
+// shell g at g*N).  fragB_*: fragment tables of B [N][K]; fragBt_f: of
+// B^T [K][N]; fragBt_h: shell_frag_halves_acc of B^T.  gs*: per-shell
+// strides in bytes.  Writes one squared-error sum per wave to partials
+// (sh2s_mse_partials of them), dc = B^T (scale (x^ - target)), and x^ when
+// xhat is not null.
+struct Sh2sMse {
+  const float *c = nullptr;
+  int64_t ldcoef = 0;
+  int K = 0;
+  const float *target = nullptr;
+  int64_t ldsig = 0;
+  int N = 0;
+  float *dc = nullptr, *xhat = nullptr;
+  const float *fragB_f = nullptr, *fragBt_f = nullptr;
+  const uint16_t *fragB_h = nullptr, *fragBt_h = nullptr;
+  int64_t gsB_f = 0, gsBt_f = 0, gsB_h = 0, gsBt_h = 0;
+  int groups = 1;
+  int64_t V = 0;
+  float scale = 0.0f;
+  float *partials = nullptr;
+};
+bool sh2s_mse_ok(int N, int K);
+int64_t sh2s_mse_partials(int64_t V, int groups);
+int launch_sh2s_mse(const Sh2sMse &t, dlm_precision prec, void *stream);
+// *out = scale * sum(partials[0..n)), one block, fixed summation order
+int launch_sum_partials(const float *partials, int64_t n, float *out, float scale, void *stream);
 
 // fill `bytes` (a multiple of 4) at p with zeros
 int launch_zero(void *p, size_t bytes, void *stream);

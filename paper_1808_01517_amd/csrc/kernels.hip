@@ -1023,6 +1023,12 @@ int launch_mse(const float *pred, const float *target, int64_t n, float *loss, f
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+int launch_sum_partials(const float *partials, int64_t n, float *out, float scale, void *stream) {
+  if (n <= 0 || n > 0x7fffffff) return -3;
+  hipLaunchKernelGGL(mse_final_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, partials, (int)n, out, scale);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_relmse(const float *pred, const float *target, int64_t n, float eps, float *loss, float *dpred,
                   float *partials, int nblocks, void *stream) {
   hipStream_t st = (hipStream_t)stream;

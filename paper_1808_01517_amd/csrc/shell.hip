@@ -153,7 +153,195 @@ int launch_op(const ShellGemm &t, dlm_precision prec, hipStream_t st) {
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// SH2Signal -> q-space MSE -> SH2Signal adjoint for 16 voxels x one shell
+// per wave (the tail of a training step, Sec. 1: the loss is taken back in
+// q-space):
+//   x^[n]  = sum_k B[n][k] c[k]                 (GEMM 1, n < N, k < K)
+//   loss  += (x^[n] - t[n])^2                   (one partial per wave)
+//   d[n]   = scale (x^[n] - t[n]),  scale = 2 / (V n_dw)
+//   dc[k]  = sum_n B[n][k] d[n]                 (GEMM 2)
+// GEMM 2 takes d straight from GEMM 1's accumulators: lane (q16, g4) holds
+// d at n = 16 j + 4 g4 + e, which is exactly the FP32 fragment order of the
+// 16-k groups (so the standard fragment table of B^T serves), and in BF16
+// a 32-k step takes tiles 2s and 2s+1 (its table is built in that order,
+// shell_frag_halves_acc).  N <= 96, K <= 64.
+template <bool F32>
+__global__ __launch_bounds__(256) void sh2s_mse_kernel(const float *c, int64_t ldcoef, int K, const float *tgt,
+                                                       int64_t ldsig, int N, float *dc, float *xhat,
+                                                       const void *fragB, const void *fragBt, int64_t gsB,
+                                                       int64_t gsBt, int groups, int64_t V, int64_t nwaves,
+                                                       float scale, float *partials) {
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= nwaves) return;  // whole waves only; no barriers in this kernel
+  const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
+  const int64_t rb = w / groups;
+  const int g = (int)(w - rb * groups);
+  const int64_t r = rb * 16 + q16;
+  const bool row = r < V;
+  const float *a = c + r * ldcoef + (int64_t)g * K;
+  const float *t = tgt + r * ldsig + (int64_t)g * N;
+  const int NT1 = (N + 15) / 16, NT2 = (K + 15) / 16;
+  floatx4 acc[kColChunk], acc2[4];
+#pragma unroll
+  for (int j = 0; j < kColChunk; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc2[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  // target values of this lane's accumulator positions, loaded up front
+  floatx4 tv[kColChunk];
+#pragma unroll
+  for (int j = 0; j < kColChunk; ++j)
+    tv[j] = j < NT1 ? load_run(t, 16 * j + 4 * g4, N, row) : floatx4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (F32) {
+    const floatx4 *f1 = reinterpret_cast<const floatx4 *>(fragB) + (int64_t)g * gsB / 16;
+    const floatx4 *f2 = reinterpret_cast<const floatx4 *>(fragBt) + (int64_t)g * gsBt / 16;
+    const int H = (K + 15) / 16;
+    floatx4 av[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) av[h] = h < H ? load_run(a, 16 * h + 4 * g4, K, row) : floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      if (h >= H) break;
+#pragma unroll
+      for (int j = 0; j < kColChunk; ++j) {
+        if (j >= NT1) break;
+        const floatx4 b = f1[((int64_t)j * H + h) * 64 + lane];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[e], av[h][e], acc[j], 0, 0, 0);
+      }
+    }
+    float lsum = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kColChunk; ++j) {
+      if (j >= NT1) break;
+      const int n = 16 * j + 4 * g4;
+      if (xhat && row) {
+        float *xo = xhat + r * ldsig + (int64_t)g * N;
+        if (n + 3 < N) __builtin_memcpy(xo + n, &acc[j], 16);
+        else
+          for (int e = 0; e < 4; ++e)
+            if (n + e < N) xo[n + e] = acc[j][e];
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float diff = row && n + e < N ? acc[j][e] - tv[j][e] : 0.0f;
+        lsum += diff * diff;
+        acc[j][e] = diff * scale;  // now d
+      }
+    }
+    // GEMM 2 over n: group h of 16 n = accumulator tile h
+#pragma unroll
+    for (int h = 0; h < kColChunk; ++h) {
+      if (h >= NT1) break;
+#pragma unroll
+      for (int j2 = 0; j2 < 4; ++j2) {
+        if (j2 >= NT2) break;
+        const floatx4 b = f2[((int64_t)j2 * NT1 + h) * 64 + lane];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc2[j2] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[e], acc[h][e], acc2[j2], 0, 0, 0);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+    if (lane == 0) partials[w] = lsum;
+  } else {
+    const bf16x8 *f1 = reinterpret_cast<const bf16x8 *>(fragB) + (int64_t)g * gsB / 16;
+    const bf16x8 *f2 = reinterpret_cast<const bf16x8 *>(fragBt) + (int64_t)g * gsBt / 16;
+    const int S = (K + 31) / 32;
+    bf16x8 av[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const floatx4 lo = s < S ? load_run(a, 32 * s + 8 * g4, K, row) : floatx4{0.f, 0.f, 0.f, 0.f};
+      const floatx4 hi = s < S ? load_run(a, 32 * s + 8 * g4 + 4, K, row) : floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        av[s][e] = (__bf16)lo[e];
+        av[s][4 + e] = (__bf16)hi[e];
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      if (s >= S) break;
+#pragma unroll
+      for (int j = 0; j < kColChunk; ++j) {
+        if (j >= NT1) break;
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f1[((int64_t)j * S + s) * 64 + lane], av[s], acc[j], 0, 0, 0);
+      }
+    }
+    float lsum = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kColChunk; ++j) {
+      if (j >= NT1) break;
+      const int n = 16 * j + 4 * g4;
+      if (xhat && row) {
+        float *xo = xhat + r * ldsig + (int64_t)g * N;
+        if (n + 3 < N) __builtin_memcpy(xo + n, &acc[j], 16);
+        else
+          for (int e = 0; e < 4; ++e)
+            if (n + e < N) xo[n + e] = acc[j][e];
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float diff = row && n + e < N ? acc[j][e] - tv[j][e] : 0.0f;
+        lsum += diff * diff;
+        acc[j][e] = diff * scale;
+      }
+    }
+    // GEMM 2: a 32-n step s takes the lane's d of tiles 2s (slots 0-3) and 2s+1 (slots 4-7)
+    const int S2 = (NT1 + 1) / 2;
+#pragma unroll
+    for (int s = 0; s < kColChunk / 2; ++s) {
+      if (s >= S2) break;
+      bf16x8 dv;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        dv[e] = (__bf16)acc[2 * s][e];
+        dv[4 + e] = (__bf16)(2 * s + 1 < NT1 ? acc[2 * s + 1][e] : 0.0f);
+      }
+#pragma unroll
+      for (int j2 = 0; j2 < 4; ++j2) {
+        if (j2 >= NT2) break;
+        acc2[j2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f2[((int64_t)j2 * S2 + s) * 64 + lane], dv, acc2[j2], 0, 0, 0);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+    if (lane == 0) partials[w] = lsum;
+  }
+  if (row) {
+    float *o = dc + r * ldcoef + (int64_t)g * K;
+#pragma unroll
+    for (int j2 = 0; j2 < 4; ++j2) {
+      if (j2 >= NT2) break;
+      const int k = 16 * j2 + 4 * g4;
+      if (k + 3 < K) __builtin_memcpy(o + k, &acc2[j2], 16);
+      else
+        for (int e = 0; e < 4; ++e)
+          if (k + e < K) o[k + e] = acc2[j2][e];
+    }
+  }
+}
+
 }  // namespace shellk
+
+bool sh2s_mse_ok(int N, int K) { return N > 0 && N <= 16 * shellk::kColChunk && K > 0 && K <= 64; }
+
+int64_t sh2s_mse_partials(int64_t V, int groups) { return (V + 15) / 16 * groups; }
+
+int launch_sh2s_mse(const Sh2sMse &t, dlm_precision prec, void *stream) {
+  if (!sh2s_mse_ok(t.N, t.K)) return -3;
+  if (t.V <= 0) return 0;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t nwaves = sh2s_mse_partials(t.V, t.groups);
+  const int64_t blocks = (nwaves + 3) / 4;
+  if (blocks > 0x7fffffff) return -4;
+  if (prec == DLM_BF16)
+    hipLaunchKernelGGL((shellk::sh2s_mse_kernel<false>), dim3((unsigned)blocks), dim3(256), 0, st, t.c, t.ldcoef, t.K,
+                       t.target, t.ldsig, t.N, t.dc, t.xhat, (const void *)t.fragB_h, (const void *)t.fragBt_h,
+                       t.gsB_h, t.gsBt_h, t.groups, t.V, nwaves, t.scale, t.partials);
+  else
+    hipLaunchKernelGGL((shellk::sh2s_mse_kernel<true>), dim3((unsigned)blocks), dim3(256), 0, st, t.c, t.ldcoef, t.K,
+                       t.target, t.ldsig, t.N, t.dc, t.xhat, (const void *)t.fragB_f, (const void *)t.fragBt_f,
+                       t.gsB_f, t.gsBt_f, t.groups, t.V, nwaves, t.scale, t.partials);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
 
 bool shell_gemm_ok(int ncol, int nred) { return ncol > 0 && nred > 0 && nred <= shellk::kMaxRed; }
 
@@ -191,6 +379,24 @@ void shell_frag_tables(const double *t, int ncol, int nred, float *f, uint16_t *
       for (int s = 0; s < S; ++s)
         for (int e = 0; e < 8; ++e) {
           const int red = 32 * s + 8 * g4 + e;
+          h[((size_t(j) * S + s) * 64 + lane) * 8 + e] =
+              col < ncol && red < nred ? f64_to_bf16_rne(t[size_t(col) * nred + red]) : uint16_t(0);
+        }
+    }
+}
+
+// bfloat16 table in the accumulator order of the fused loss head: entry
+// ((j*S + s)*64 + lane)*8 + e holds Bt[16 j + lane % 16][n(s, e)] with
+// n = 32 s + 4 (lane / 16) + e for e < 4 and 32 s + 16 + 4 (lane / 16) + e - 4
+// for e >= 4 (zero outside).  Same size as shell_frag_halves.
+void shell_frag_halves_acc(const double *t, int ncol, int nred, uint16_t *h) {
+  const int NT = (ncol + 15) / 16, S = (nred + 31) / 32;
+  for (int j = 0; j < NT; ++j)
+    for (int lane = 0; lane < 64; ++lane) {
+      const int col = 16 * j + (lane & 15), g4 = lane >> 4;
+      for (int s = 0; s < S; ++s)
+        for (int e = 0; e < 8; ++e) {
+          const int red = 32 * s + (e < 4 ? 4 * g4 + e : 16 + 4 * g4 + e - 4);
           h[((size_t(j) * S + s) * 64 + lane) * 8 + e] =
               col < ncol && red < nred ? f64_to_bf16_rne(t[size_t(col) * nred + red]) : uint16_t(0);
         }

@@ -19,7 +19,8 @@ import numpy as np
 import torch
 
 from . import (DEFAULT_FORM, LSCPlan, SHPlan, Workspace, adam_step, lib, lsc_bwd, lsc_fwd, lsc_workspace_bytes,
-               mse_fwd_bwd, sh2signal_bwd, sh2signal_fwd, signal2sh_bwd, signal2sh_fwd)
+               mse_fwd_bwd, sh2signal_bwd, sh2signal_fwd, sh2signal_mse_fwd_bwd, sh2signal_mse_supported,
+               signal2sh_bwd, signal2sh_fwd)
 
 
 @dataclass
@@ -87,6 +88,12 @@ class LSCNetwork:
         self.loss = torch.empty((), **f32)
         self.mse_ws = torch.empty(lib().dlm_mse_workspace_bytes(V * self.plan_out.n_dw), dtype=torch.uint8,
                                   device=self.dev)
+        # the fused loss head (SH2Signal, MSE and its adjoint in one pass)
+        # when the output table allows it; dxhat is then not materialised
+        self.fused_head = sh2signal_mse_supported(self.plan_out)
+        if self.fused_head:
+            self.head_ws = torch.empty(lib().dlm_sh2signal_mse_workspace_bytes(self.plan_out.handle, V),
+                                       dtype=torch.uint8, device=self.dev)
 
     def parameters(self):
         return self.W + self.b
@@ -106,19 +113,27 @@ class LSCNetwork:
         lsc_fwd(p, self.acts[k][:V], self.W[k], self.b[k], relu=s.relu, out=self.acts[k + 1][:V],
                 precision=self.precision, workspace=self.ws, form=self.form)
 
-    def forward(self, x: torch.Tensor) -> torch.Tensor:
+    def _forward_sh(self, x: torch.Tensor) -> int:
         V = x.shape[0]
         if V > self.cap:
             self._alloc(V)
         signal2sh_fwd(self.plan_in, x, out=self.acts[0][:V], precision=self.precision)
         for k in range(len(self.specs)):
             self._layer_fwd(k, V)
+        return V
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        V = self._forward_sh(x)
         sh2signal_fwd(self.plan_out, self.acts[-1][:V], out=self.xhat[:V], precision=self.precision)
         return self.xhat[:V]
 
     def backward(self, V: int, need_input_grad=False):
-        """Gradients of the last loss w.r.t. every weight (and the input when asked)."""
+        """Gradients of the last loss w.r.t. every weight (and the input when
+        asked), from the q-space gradient in `dxhat`."""
         sh2signal_bwd(self.plan_out, self.dxhat[:V], out=self.grads[-1][:V], precision=self.precision)
+        return self._backward_layers(V, need_input_grad)
+
+    def _backward_layers(self, V: int, need_input_grad: bool):
         n = len(self.specs)
         for k in range(n - 1, -1, -1):
             s, p = self.specs[k], self.plans[k]
@@ -138,11 +153,17 @@ class LSCNetwork:
         return None
 
     def loss_and_grads(self, x: torch.Tensor, target: torch.Tensor, need_input_grad=False):
-        V = x.shape[0]
-        self.forward(x)
-        mse_fwd_bwd(self.xhat[:V], target, outs=(self.loss, self.dxhat[:V], self.mse_ws))
-        dx = self.backward(V, need_input_grad)
-        return self.loss, dx
+        """Forward, q-space MSE against `target` and backward; the prediction
+        is left in `xhat`."""
+        if not self.fused_head:
+            V = x.shape[0]
+            self.forward(x)
+            mse_fwd_bwd(self.xhat[:V], target, outs=(self.loss, self.dxhat[:V], self.mse_ws))
+            return self.loss, self.backward(V, need_input_grad)
+        V = self._forward_sh(x)
+        sh2signal_mse_fwd_bwd(self.plan_out, self.acts[-1][:V], target, precision=self.precision,
+                              outs=(self.loss, self.grads[-1][:V], self.head_ws), xhat_out=self.xhat[:V])
+        return self.loss, self._backward_layers(V, need_input_grad)
 
     def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         self.t += 1
