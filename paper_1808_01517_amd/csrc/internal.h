@@ -87,6 +87,8 @@ int launch_table_gemm(const TableGemm &g, dlm_precision prec, void *stream);
 bool stream_table_ok(const TableGemm &g, dlm_precision prec);
 int launch_stream_table(const TableGemm &g, dlm_precision prec, void *stream);
 // Weight-gradient form of launch_lsc_fold_grad (no mask), ksplit a multiple of 32.
+// whether launch_stream_grad takes these sizes (ksplit: voxels per split)
+bool stream_grad_ok(int M, int CK, int ksplit);
 int launch_stream_grad(const float *g, const float *a, int64_t V, int M, int CK, int splits, int ksplit,
                        float *partial, dlm_precision prec, void *stream);
 // Per-shell SH contraction, one wave per 16 voxels x one shell (groups

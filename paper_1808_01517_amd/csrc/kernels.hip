@@ -853,7 +853,8 @@ int launch_lsc_fold_grad(const float *da_out, const float *mask, const float *a_
   const int N1 = CK + 1;
   const int ks = split_len(V, splits);
   if ((V + ks - 1) / ks != splits) return -2;
-  if (!mask) return launch_stream_grad(da_out, a_in, V, M, CK, splits, ks, partial, prec, stream);
+  if (!mask && stream_grad_ok(M, CK, ks))
+    return launch_stream_grad(da_out, a_in, V, M, CK, splits, ks, partial, prec, stream);
   hipStream_t st = (hipStream_t)stream;
   const Shape sh = grad_shape(M, N1);
   if (M >= N1) {

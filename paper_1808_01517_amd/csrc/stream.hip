@@ -13,12 +13,15 @@
 //   NS stages, so NS-1 slices of 32 k are in flight while one is multiplied.
 // * Float32 operands stay float32 in LDS and are rounded to bfloat16 (RNE)
 //   when a wave reads its MFMA fragment; bfloat16 tables are copied as is.
-//   Lanes whose reduction index lies at or beyond the end of the range copy
-//   zeros from a 4 KB zero buffer (spread over lanes, so no single cache
-//   line is hot); the weight gradient's ones row is written into every ring
-//   slot once at kernel start and skipped by the DMA.  LDS thus holds the
-//   exact operands and fragment reads need no conditionals.  Rows beyond the
-//   matrix are clamped to valid rows (their outputs are never stored).
+//   A stage wholly inside the reduction range copies from one wave-uniform
+//   base address plus per-lane 32-bit offsets computed once per block, so
+//   the loop spends a scalar add and one instruction per copy.  In the one
+//   stage where the range ends, lanes at or beyond the end copy zeros from a
+//   4 KB zero buffer (spread over lanes, so no single cache line is hot).
+//   LDS thus holds the exact operands and fragment reads need no
+//   conditionals.  Rows beyond the matrix are clamped to valid rows (their
+//   outputs are never stored); the weight gradient's ones row is one of
+//   them, and its fragments are set to ones in registers.
 // * Every LDS layout is swizzled so that fragment reads avoid bank
 //   conflicts while each DMA instruction still fills 64 consecutive slots
 //   (the hardware writes lane i of an instruction to base + i * size).
@@ -120,8 +123,25 @@ struct SKc {
     if (gk >= kend) return zeros_for(s);
     return p + gr * ld + gk;
   }
+  // Stage with every k inside the range: lane s copies from
+  // base(r0, k0) + lane_off(s, r0) bytes.
+  __device__ const char *base(int64_t r0, int k0) const {
+    return reinterpret_cast<const char *>(p + r0 * ld + k0);
+  }
   template <int BR>
-  __device__ void init_lds(char *, int, int, int64_t, int) const {}
+  __device__ uint32_t lane_off(int s, int64_t r0) const {
+    int r, k;
+    if constexpr (VEC) {
+      r = s >> 3;
+      k = ((s & 7) ^ (r & 7)) << 2;
+    } else {
+      r = s >> 5;
+      k = ((((s >> 2) & 7) ^ (r & 7)) << 2) | (s & 3);
+    }
+    const int64_t gr = r0 + r < rows ? r0 + r : rows - 1;
+    return (uint32_t)(((gr - r0) * ld + k) * 4);
+  }
+  __device__ void bind(int64_t) {}
   template <int BR>
   __device__ bf16x8 frag(const char *lds, int rg, int q16, int g4) const {
     const int r = rg * 16 + q16;
@@ -140,7 +160,8 @@ struct SKc {
 };
 
 // Row-contiguous float32: element (r, k) at p[k * ld + r], valid for
-// r < rows, k < kend; row `ones` (if >= 0) reads as 1 for k < kend.
+// r < rows, k < kend; row `ones` (if >= 0) reads as 1 (bind() locates it in
+// the block's tile).
 // LDS: [32][BR] floats (k-major); row r of k-line k is stored at
 // (r + 16 h(k)) mod BR with h(k) = bit 2 xor bit 3 of k, so the lanes of a
 // fragment read that differ in k land 16 banks apart.  VEC needs 16-byte
@@ -149,6 +170,7 @@ template <bool VEC>
 struct SRc {
   const float *p;
   int64_t ld, rows, ones;
+  int orel = -1;  // row `ones` relative to the bound tile, -1 if outside
   static constexpr int kUnit = VEC ? 16 : 4;
   template <int BR>
   static constexpr int bytes() { return BR * SBK * 4; }
@@ -170,27 +192,54 @@ struct SRc {
       r = s - k * BR - 16 * hk(k);
       if (r < 0) r += BR;
     }
-    const int64_t gr = r0 + r;
     if (k0 + k >= kend) return zeros_for(s);
-    if (gr == ones) return nullptr;  // preset in LDS by init_lds
-    return p + (int64_t)(k0 + k) * ld + (gr >= rows ? 0 : gr);
+    return p + (int64_t)(k0 + k) * ld + clamp(r0 + r);
   }
-  // Write the ones row (and, for 16-byte lanes, zeros in the rest of its
-  // chunk, rows never stored) into all ns ring slots; stride: slot bytes.
+  // rows beyond the matrix (the ones row among them: its fragments are set
+  // in registers) copy the last row, or for 16-byte lanes the last chunk
+  static constexpr int kLast = VEC ? 4 : 1;
+  __device__ int64_t clamp(int64_t gr) const { return gr < rows ? gr : rows - kLast; }
+  // A tile may start at or past the last row (the ones row is row `rows`),
+  // so full-stage addresses are taken relative to the clamped tile start,
+  // never above any clamped row: offsets stay non-negative.
+  __device__ int64_t rbase(int64_t r0) const { return r0 < rows - kLast ? r0 : rows - kLast; }
+  __device__ const char *base(int64_t r0, int k0) const {
+    return reinterpret_cast<const char *>(p + (int64_t)k0 * ld + rbase(r0));
+  }
   template <int BR>
-  __device__ void init_lds(char *base, int ns, int stride, int64_t r0, int tid) const {
-    const int64_t ro = ones - r0;
-    if (ones < 0 || ro < 0 || ro >= BR) return;
-    const int slot = tid >> 5, k = tid & 31;
-    if (slot >= ns) return;
-    float *t = reinterpret_cast<float *>(base + slot * stride);
-    const int pos = ((int)ro + 16 * hk(k)) % BR;
-    t[k * BR + pos] = 1.0f;
-    if constexpr (VEC)
-      for (int q = 1; q < 4; ++q) t[k * BR + pos + q] = 0.0f;
+  __device__ uint32_t lane_off(int s, int64_t r0) const {
+    int k, r;
+    if constexpr (VEC) {
+      constexpr int NC = BR / 4;
+      k = s / NC;
+      int rc = s - k * NC - 4 * hk(k);
+      if (rc < 0) rc += NC;
+      r = 4 * rc;
+    } else {
+      k = s / BR;
+      r = s - k * BR - 16 * hk(k);
+      if (r < 0) r += BR;
+    }
+    return (uint32_t)(((int64_t)k * ld + (clamp(r0 + r) - rbase(r0))) * 4);
   }
+  __device__ void bind(int64_t r0) {
+    const int64_t ro = ones - r0;
+    orel = ones >= 0 && ro >= 0 && ro < 1 << 20 ? (int)ro : -1;
+  }
+  // the ones row, for every k: a whole fragment of ones (the other operand
+  // is zero beyond the range, so the padding contributes nothing)
+  __device__ bool ones_group(int rg) const { return orel >= 16 * rg && orel < 16 * rg + 16; }
   template <int BR>
   __device__ bf16x8 frag(const char *lds, int rg, int q16, int g4) const {
+    bf16x8 v = frag_lds<BR>(lds, rg, q16, g4);
+    if (ones_group(rg) && q16 == orel - 16 * rg) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (__bf16)1.0f;
+    }
+    return v;
+  }
+  template <int BR>
+  __device__ bf16x8 frag_lds(const char *lds, int rg, int q16, int g4) const {
     constexpr int NG = BR / 16;
     const float *t = reinterpret_cast<const float *>(lds);
     // h(8 g4 + e) = (e >> 2) ^ (g4 & 1): position group rg + h (mod NG)
@@ -214,6 +263,7 @@ struct SRc {
     floatx4 v;
 #pragma unroll
     for (int j = 0; j < 4; ++j) v[j] = t[(16 * h + 4 * g4 + j) * BR + pg * 16 + q16];
+    if (ones_group(rg) && q16 == orel - 16 * rg) v = floatx4{1.f, 1.f, 1.f, 1.f};
     return v;
   }
 };
@@ -230,14 +280,19 @@ struct SKh {
   template <int BR>
   static constexpr int slots() { return bytes<BR>() / kUnit; }
   template <int BR>
-  __device__ void init_lds(char *, int, int, int64_t, int) const {}
-  template <int BR>
   __device__ const uint16_t *src(int s, int64_t r0, int k0, int) const {
-    const int r = s >> 2, c = (s & 3) ^ ((r >> 1) & 3);
-    int64_t gr = r0 + r;
-    if (gr >= rows) gr = rows - 1;
-    return p + gr * ldp + k0 + 8 * c;
+    return reinterpret_cast<const uint16_t *>(base(r0, k0) + lane_off<BR>(s, r0));
   }
+  __device__ const char *base(int64_t r0, int k0) const {
+    return reinterpret_cast<const char *>(p + r0 * ldp + k0);
+  }
+  template <int BR>
+  __device__ uint32_t lane_off(int s, int64_t r0) const {
+    const int r = s >> 2, c = (s & 3) ^ ((r >> 1) & 3);
+    const int64_t gr = r0 + r < rows ? r0 + r : rows - 1;
+    return (uint32_t)(((gr - r0) * ldp + 8 * c) * 2);
+  }
+  __device__ void bind(int64_t) {}
   template <int BR>
   __device__ bf16x8 frag(const char *lds, int rg, int q16, int g4) const {
     const int r = rg * 16 + q16;
@@ -372,9 +427,48 @@ __device__ __forceinline__ void dma_stage(const OPND &op, char *dst, int first, 
   for (int i = 0; i < (NI + step - 1) / step; ++i) {
     const int inst = first + step * i;
     const int s = inst * 64 + lane;
-    if (inst < NI && s < NSL) {
-      const void *src = op.template src<BR>(s, r0, k0, kend);
-      if (src) dma_to_lds<OPND::kUnit>(src, dst + inst * 64 * OPND::kUnit);
+    if (inst < NI && s < NSL) dma_to_lds<OPND::kUnit>(op.template src<BR>(s, r0, k0, kend), dst + inst * 64 * OPND::kUnit);
+  }
+}
+
+// Number of DMA instructions of an operand that wave `first` (of `step`)
+// issues per stage, at most.
+template <int BR, class OPND>
+constexpr int dma_per_wave(int step) {
+  return ((OPND::template slots<BR>() + 63) / 64 + step - 1) / step;
+}
+
+// Byte offsets of the lane's DMA copies within a full stage (loop-invariant).
+template <int BR, class OPND, int NW>
+__device__ __forceinline__ void dma_offsets(const OPND &op, uint32_t (&off)[NW], int first, int step, int lane,
+                                            int64_t r0) {
+  constexpr int NSL = OPND::template slots<BR>();
+  constexpr int NI = (NSL + 63) / 64;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    const int inst = first + step * i;
+    const int s = inst * 64 + lane;
+    off[i] = inst < NI && s < NSL ? op.template lane_off<BR>(s, r0) : 0u;
+  }
+}
+
+// A full stage: every lane copies from the stage's wave-uniform base plus
+// its precomputed offset.  The offset passes through an empty asm inside the
+// loop so that its zero extension stays next to the add and the copy is
+// selected in the scalar-base + 32-bit vector-offset form (a hoisted 64-bit
+// offset would cost a 64-bit add and two registers per copy).
+template <int BR, class OPND, int STEP, int NW>
+__device__ __forceinline__ void dma_stage_full(const char *base, const uint32_t (&off)[NW], char *dst, int first,
+                                               int lane) {
+  constexpr int NSL = OPND::template slots<BR>();
+  constexpr int NI = (NSL + 63) / 64;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    const int inst = first + STEP * i;
+    if ((NI % STEP == 0 || inst < NI) && (NSL % 64 == 0 || inst * 64 + lane < NSL)) {
+      uint32_t o = off[i];
+      asm volatile("" : "+v"(o));
+      dma_to_lds<OPND::kUnit>(base + o, dst + inst * 64 * OPND::kUnit);
     }
   }
 }
@@ -412,11 +506,24 @@ __global__ __launch_bounds__(256) void gemm_stream_kernel(AO ao, BO bo, CS cs, i
   }
   const int niter = kend > kbeg ? (kend - kbeg + SBK - 1) / SBK : 0;
 
+  AO aw = ao;
+  BO bw = bo;
+  aw.bind(m0);
+  bw.bind(n0);
+  constexpr int NWA = dma_per_wave<BM, AO>(4), NWB = dma_per_wave<BN, BO>(4);
+  uint32_t offa[NWA], offb[NWB];
+  dma_offsets<BM>(ao, offa, wave, 4, lane, m0);
+  dma_offsets<BN>(bo, offb, wave, 4, lane, n0);
   auto issue = [&](int it) {
     char *sa = lds + (it % NS) * SB;
     const int k0 = kbeg + it * SBK;
-    dma_stage<BM>(ao, sa, wave, 4, lane, m0, k0, kend);
-    dma_stage<BN>(bo, sa + AB, wave, 4, lane, n0, k0, kend);
+    if (k0 + SBK <= kend) {
+      dma_stage_full<BM, AO, 4>(ao.base(m0, k0), offa, sa, wave, lane);
+      dma_stage_full<BN, BO, 4>(bo.base(n0, k0), offb, sa + AB, wave, lane);
+    } else {  // the range ends inside this stage: checked copies, zeros beyond
+      dma_stage<BM>(ao, sa, wave, 4, lane, m0, k0, kend);
+      dma_stage<BN>(bo, sa + AB, wave, 4, lane, n0, k0, kend);
+    }
   };
 
   floatx4 acc[CF::TM][CF::TN];
@@ -425,8 +532,6 @@ __global__ __launch_bounds__(256) void gemm_stream_kernel(AO ao, BO bo, CS cs, i
 #pragma unroll
     for (int j = 0; j < CF::TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  ao.template init_lds<BM>(lds, NS, SB, m0, tid);
-  bo.template init_lds<BN>(lds + AB, NS, SB, n0, tid);
 #pragma unroll
   for (int s = 0; s < D; ++s)
     if (s < niter) issue(s);
@@ -448,7 +553,7 @@ __global__ __launch_bounds__(256) void gemm_stream_kernel(AO ao, BO bo, CS cs, i
     wait_issue(it);
     const char *sa = lds + (it % NS) * SB;
     const int nh = kend - (kbeg + it * SBK) > 16 ? 2 : 1;
-    mma_stage<CF, F32>(ao, bo, sa, sa + AB, wm, wn, q16, g4, nh, acc);
+    mma_stage<CF, F32>(aw, bw, sa, sa + AB, wm, wn, q16, g4, nh, acc);
   }
   store_tiles<CF>(cs, acc, M, N, m0, n0, wm, wn, q16, g4, z);
 }
@@ -552,8 +657,12 @@ int stream_grad(AO ao, BO bo, CS cs, int64_t rows, int cols, int64_t V, int spli
 
 using namespace streaming;
 
+// Full-stage DMA offsets are 32-bit: a tile's rows must span < 4 GiB.
+constexpr int64_t kMaxStreamLd = int64_t(1) << 22;
+
 bool stream_table_ok(const TableGemm &t, dlm_precision prec) {
   if (t.groups != 1 || t.mask != nullptr || (t.op != kOpFoldFwd && t.op != kOpFoldBwdData)) return false;
+  if (t.lda >= kMaxStreamLd || t.ldb_f >= kMaxStreamLd || t.ldb_h >= kMaxStreamLd) return false;
   if (t.op == kOpFoldFwd ? (t.bias_n == nullptr || t.out_mask != nullptr) : t.bias_n != nullptr) return false;
   if (prec == DLM_BF16)
     return t.Bh != nullptr && t.ldb_h > 0 && t.ldb_h % SBK == 0 && t.ldb_h >= t.K && aligned16(t.Bh);
@@ -593,9 +702,13 @@ static int stream_grad_p(const float *g, const float *a, int64_t V, int M, int C
   return stream_grad<F32>(SRc<false>{a, CK, CK, CK}, SRc<false>{g, M, M, -1}, cs, N1, M, V, splits, ksplit, st);
 }
 
+bool stream_grad_ok(int M, int CK, int ksplit) {
+  return ksplit % SBK == 0 && M < kMaxStreamLd && CK < kMaxStreamLd;
+}
+
 int launch_stream_grad(const float *g, const float *a, int64_t V, int M, int CK, int splits, int ksplit,
                        float *partial, dlm_precision prec, void *stream) {
-  if (ksplit % SBK != 0) return -2;
+  if (!stream_grad_ok(M, CK, ksplit)) return -2;
   hipStream_t st = (hipStream_t)stream;
   if (prec == DLM_BF16) return stream_grad_p<false>(g, a, V, M, CK, splits, ksplit, partial, st);
   return stream_grad_p<true>(g, a, V, M, CK, splits, ksplit, partial, st);
