@@ -90,9 +90,10 @@ __device__ __forceinline__ bf16x8 to_bf16x8(floatx4 lo, floatx4 hi) {
 // ------------------------------------------------------ streamed operands
 // Each operand type gives, for a tile of BR rows and one stage of SBK
 // reduction entries: bytes() of LDS, slots() DMA lanes of kUnit bytes,
-// src(slot) the global address the lane copies, and frag() the bfloat16
-// MFMA fragment of 16 rows (row group rg) x 8 k for lane (q16, g4):
-// row rg*16 + q16, k = 8*g4 .. 8*g4 + 7.
+// base(r0, k0) + lane_off(slot, r0) the global address slot `slot` copies,
+// k_of(slot) its reduction index within the stage (for zero padding), and
+// frag() the bfloat16 MFMA fragment of 16 rows (row group rg) x 8 k for lane
+// (q16, g4): row rg*16 + q16, k = 8*g4 .. 8*g4 + 7.
 
 // k-contiguous float32: element (r, k) at p[r * ld + k], valid for r < rows,
 // k < kend.  LDS: [BR][32] floats, 4-float chunk c of row r stored at chunk
@@ -107,22 +108,6 @@ struct SKc {
   static constexpr int bytes() { return BR * SBK * 4; }
   template <int BR>
   static constexpr int slots() { return bytes<BR>() / kUnit; }
-  template <int BR>
-  __device__ const float *src(int s, int64_t r0, int k0, int kend) const {
-    int r, k;
-    if constexpr (VEC) {
-      r = s >> 3;
-      k = ((s & 7) ^ (r & 7)) << 2;
-    } else {
-      r = s >> 5;
-      k = ((((s >> 2) & 7) ^ (r & 7)) << 2) | (s & 3);
-    }
-    int64_t gr = r0 + r;
-    if (gr >= rows) gr = rows - 1;
-    const int gk = k0 + k;
-    if (gk >= kend) return zeros_for(s);
-    return p + gr * ld + gk;
-  }
   // Stage with every k inside the range: lane s copies from
   // base(r0, k0) + lane_off(s, r0) bytes.
   __device__ const char *base(int64_t r0, int k0) const {
@@ -140,6 +125,12 @@ struct SKc {
     }
     const int64_t gr = r0 + r < rows ? r0 + r : rows - 1;
     return (uint32_t)(((gr - r0) * ld + k) * 4);
+  }
+  // reduction index (within the stage) of slot s: its first, for 16-byte lanes
+  template <int BR>
+  __device__ static int k_of(int s) {
+    if constexpr (VEC) return ((s & 7) ^ ((s >> 3) & 7)) << 2;
+    else return ((((s >> 2) & 7) ^ ((s >> 5) & 7)) << 2) | (s & 3);
   }
   __device__ void bind(int64_t) {}
   template <int BR>
@@ -177,24 +168,6 @@ struct SRc {
   template <int BR>
   static constexpr int slots() { return bytes<BR>() / kUnit; }
   __device__ static int hk(int k) { return ((k >> 2) ^ (k >> 3)) & 1; }
-  template <int BR>
-  __device__ const float *src(int s, int64_t r0, int k0, int kend) const {
-    static_assert(BR % 16 == 0, "row tile");
-    int k, r;
-    if constexpr (VEC) {
-      constexpr int NC = BR / 4;
-      k = s / NC;
-      int rc = s - k * NC - 4 * hk(k);
-      if (rc < 0) rc += NC;
-      r = 4 * rc;
-    } else {
-      k = s / BR;
-      r = s - k * BR - 16 * hk(k);
-      if (r < 0) r += BR;
-    }
-    if (k0 + k >= kend) return zeros_for(s);
-    return p + (int64_t)(k0 + k) * ld + clamp(r0 + r);
-  }
   // rows beyond the matrix (the ones row among them: its fragments are set
   // in registers) copy the last row, or for 16-byte lanes the last chunk
   static constexpr int kLast = VEC ? 4 : 1;
@@ -208,6 +181,7 @@ struct SRc {
   }
   template <int BR>
   __device__ uint32_t lane_off(int s, int64_t r0) const {
+    static_assert(BR % 16 == 0, "row tile");
     int k, r;
     if constexpr (VEC) {
       constexpr int NC = BR / 4;
@@ -221,6 +195,11 @@ struct SRc {
       if (r < 0) r += BR;
     }
     return (uint32_t)(((int64_t)k * ld + (clamp(r0 + r) - rbase(r0))) * 4);
+  }
+  template <int BR>
+  __device__ static int k_of(int s) {
+    if constexpr (VEC) return s / (BR / 4);
+    else return s / BR;
   }
   __device__ void bind(int64_t r0) {
     const int64_t ro = ones - r0;
@@ -279,10 +258,6 @@ struct SKh {
   static constexpr int bytes() { return BR * SBK * 2; }
   template <int BR>
   static constexpr int slots() { return bytes<BR>() / kUnit; }
-  template <int BR>
-  __device__ const uint16_t *src(int s, int64_t r0, int k0, int) const {
-    return reinterpret_cast<const uint16_t *>(base(r0, k0) + lane_off<BR>(s, r0));
-  }
   __device__ const char *base(int64_t r0, int k0) const {
     return reinterpret_cast<const char *>(p + r0 * ldp + k0);
   }
@@ -292,6 +267,9 @@ struct SKh {
     const int64_t gr = r0 + r < rows ? r0 + r : rows - 1;
     return (uint32_t)(((gr - r0) * ldp + 8 * c) * 2);
   }
+  // the table is zero-padded to a whole stage: no copy lies beyond the range
+  template <int BR>
+  __device__ static int k_of(int) { return 0; }
   __device__ void bind(int64_t) {}
   template <int BR>
   __device__ bf16x8 frag(const char *lds, int rg, int q16, int g4) const {
@@ -416,18 +394,21 @@ __device__ __forceinline__ void store_tiles(const CS &cs, const floatx4 (&acc)[C
   }
 }
 
-// DMA of one stage's share: instructions first, first + step, ... of the
-// operand's ceil(slots / 64) instructions.
-template <int BR, class OPND>
-__device__ __forceinline__ void dma_stage(const OPND &op, char *dst, int first, int step, int lane, int64_t r0, int k0,
-                                          int kend) {
+// The stage where the range ends (krem = kend - k0 < SBK reduction entries
+// left): lanes whose entries lie beyond it copy zeros instead.
+template <int BR, class OPND, int STEP, int NW>
+__device__ __forceinline__ void dma_stage_tail(const char *base, const uint32_t (&off)[NW], char *dst, int first,
+                                               int lane, int krem) {
   constexpr int NSL = OPND::template slots<BR>();
   constexpr int NI = (NSL + 63) / 64;
 #pragma unroll
-  for (int i = 0; i < (NI + step - 1) / step; ++i) {
-    const int inst = first + step * i;
+  for (int i = 0; i < NW; ++i) {
+    const int inst = first + STEP * i;
     const int s = inst * 64 + lane;
-    if (inst < NI && s < NSL) dma_to_lds<OPND::kUnit>(op.template src<BR>(s, r0, k0, kend), dst + inst * 64 * OPND::kUnit);
+    if ((NI % STEP == 0 || inst < NI) && (NSL % 64 == 0 || s < NSL)) {
+      const void *src = OPND::template k_of<BR>(s) < krem ? (const void *)(base + off[i]) : (const void *)zeros_for(s);
+      dma_to_lds<OPND::kUnit>(src, dst + inst * 64 * OPND::kUnit);
+    }
   }
 }
 
@@ -520,9 +501,9 @@ __global__ __launch_bounds__(256) void gemm_stream_kernel(AO ao, BO bo, CS cs, i
     if (k0 + SBK <= kend) {
       dma_stage_full<BM, AO, 4>(ao.base(m0, k0), offa, sa, wave, lane);
       dma_stage_full<BN, BO, 4>(bo.base(n0, k0), offb, sa + AB, wave, lane);
-    } else {  // the range ends inside this stage: checked copies, zeros beyond
-      dma_stage<BM>(ao, sa, wave, 4, lane, m0, k0, kend);
-      dma_stage<BN>(bo, sa + AB, wave, 4, lane, n0, k0, kend);
+    } else {  // the range ends inside this stage: zeros beyond it
+      dma_stage_tail<BM, AO, 4>(ao.base(m0, k0), offa, sa, wave, lane, kend - k0);
+      dma_stage_tail<BN, BO, 4>(bo.base(n0, k0), offb, sa + AB, wave, lane, kend - k0);
     }
   };
 
@@ -609,6 +590,9 @@ struct CRowSide {
 };
 
 using SCfgWide = SCfg<128, 96, 2, 2, 3>;    // N = 1440, 2880: 15 / 30 tiles exactly
+// FP32 (two-stage ring): 64-row tiles hold four blocks per CU, which keeps the
+// matrix cores fed through the short (K = 135) reduction and the epilogue
+using SCfgWideF32 = SCfg<64, 96, 2, 2, 2>;
 using SCfgNarrow = SCfg<128, 144, 4, 1, 3>; // 96 < N <= 144 (N = 135, 136)
 using SCfgSmall = SCfg<128, 48, 4, 1, 3>;   // N <= 96
 // weight gradient: two float32 operands per stage (34 KB); a two-stage ring
@@ -619,7 +603,8 @@ template <int OP, bool F32, class AO, class BO, class CS>
 int stream_table_c(AO ao, BO bo, CS cs, const TableGemm &t, hipStream_t st) {
   if (t.N <= 96) return run_stream<OP, SCfgSmall, F32>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
   if (t.N <= 144) return run_stream<OP, SCfgNarrow, F32>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
-  return run_stream<OP, SCfgWide, F32>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
+  if constexpr (F32) return run_stream<OP, SCfgWideF32, F32>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
+  else return run_stream<OP, SCfgWide, F32>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
 }
 
 // the forward GEMM adds the folded bias; the input-gradient GEMM may mask
