@@ -576,7 +576,7 @@ int64_t sh2s_mse_waves(const dlm_sh_plan *p, int64_t V) {
 
 size_t dlm_sh2signal_mse_workspace_bytes(const dlm_sh_plan *p, int64_t V) {
   if (!p) return 0;
-  return align256(size_t(sh2s_mse_waves(p, std::max<int64_t>(V, 1))) * 4);
+  return align256(size_t(sh2s_mse_waves(p, std::max<int64_t>(V, 1)) + kSumBlocks) * 4);
 }
 
 dlm_status dlm_sh2signal_mse_fwd_bwd(const dlm_sh_plan *p, const float *c, const float *target, int64_t V,
@@ -629,7 +629,7 @@ dlm_status dlm_sh2signal_mse_fwd_bwd(const dlm_sh_plan *p, const float *c, const
     if (launch_sh2s_mse(t, prec, stream) != 0)
       return fail(DLM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
   }
-  if (launch_sum_partials(partials, pw, loss, float(1.0 / numel), stream) != 0)
+  if (launch_sum_scaled(partials, pw, loss, float(1.0 / numel), partials + pw, stream) != 0)
     return fail(DLM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
   return ok();
 }

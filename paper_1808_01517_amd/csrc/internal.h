@@ -143,8 +143,10 @@ struct Sh2sMse {
 bool sh2s_mse_ok(int N, int K);
 int64_t sh2s_mse_partials(int64_t V, int groups);
 int launch_sh2s_mse(const Sh2sMse &t, dlm_precision prec, void *stream);
-// *out = scale * sum(partials[0..n)), one block, fixed summation order
-int launch_sum_partials(const float *partials, int64_t n, float *out, float scale, void *stream);
+// *out = scale * sum(partials[0..n)) in a fixed summation order; beyond 4096
+// partials, two passes through scratch[kSumBlocks]
+constexpr int kSumBlocks = 256;
+int launch_sum_scaled(const float *partials, int64_t n, float *out, float scale, float *scratch, void *stream);
 
 // fill `bytes` (a multiple of 4) at p with zeros
 int launch_zero(void *p, size_t bytes, void *stream);

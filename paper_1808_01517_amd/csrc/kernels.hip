@@ -1024,9 +1024,34 @@ int launch_mse(const float *pred, const float *target, int64_t n, float *loss, f
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_sum_partials(const float *partials, int64_t n, float *out, float scale, void *stream) {
+// sums[b] = sum of partials[b*chunk .. min(n, (b+1)*chunk)), one block each
+__global__ __launch_bounds__(256) void sum_chunks_kernel(const float *partials, int64_t n, int64_t chunk,
+                                                         float *sums) {
+  __shared__ float red[256];
+  const int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = b0 + chunk < n ? b0 + chunk : n;
+  float s = 0.0f;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) s += partials[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+}
+
+int launch_sum_scaled(const float *partials, int64_t n, float *out, float scale, float *scratch, void *stream) {
   if (n <= 0 || n > 0x7fffffff) return -3;
-  hipLaunchKernelGGL(mse_final_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, partials, (int)n, out, scale);
+  hipStream_t st = (hipStream_t)stream;
+  if (n <= 4096) {
+    hipLaunchKernelGGL(mse_final_kernel, dim3(1), dim3(256), 0, st, partials, (int)n, out, scale);
+  } else {
+    // two passes in a fixed order: kSumBlocks chunk sums, then one block
+    const int64_t chunk = (n + kSumBlocks - 1) / kSumBlocks;
+    const int nb = (int)((n + chunk - 1) / chunk);
+    hipLaunchKernelGGL(sum_chunks_kernel, dim3(nb), dim3(256), 0, st, partials, n, chunk, scratch);
+    hipLaunchKernelGGL(mse_final_kernel, dim3(1), dim3(256), 0, st, scratch, nb, out, scale);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

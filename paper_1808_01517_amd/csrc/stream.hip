@@ -325,12 +325,58 @@ __device__ __forceinline__ void mma_stage(const AO &ao, const BO &bo, const char
   }
 }
 
+// Side inputs (bias of the lane's columns, mask of its elements) of a
+// wave's tiles, loaded ahead of the epilogue when they fit in registers
+// (at most 12 tiles per wave).
+template <class CF, class CS>
+struct SidePre {
+  static constexpr bool kOn = CS::kSide && CF::TM * CF::TN <= 12;
+  floatx4 cb[CF::TN];
+  floatx4 em[CF::TM][CF::TN];
+};
+
+template <class CF, class CS>
+__device__ __forceinline__ void load_side(const CS &cs, SidePre<CF, CS> &sp, int64_t M, int N, int64_t m0, int n0,
+                                          int wm, int wn, int q16, int g4, int z) {
+#pragma unroll
+  for (int j = 0; j < CF::TN; ++j) {
+    const int n = n0 + (wn * CF::TN + j) * 16 + 4 * g4;
+    sp.cb[j] = n + 3 < N ? cs.colside(n) : floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+#pragma unroll
+  for (int i = 0; i < CF::TM; ++i) {
+    const int64_t r = m0 + (wm * CF::TM + i) * 16 + q16;
+#pragma unroll
+    for (int j = 0; j < CF::TN; ++j) {
+      const int n = n0 + (wn * CF::TN + j) * 16 + 4 * g4;
+      sp.em[i][j] = r < M && n + 3 < N ? cs.elside(r, n, z) : floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+  }
+}
+
 // Store a consumer wave's tiles: lane (q16, g4) holds row m0 + (wm*TM+i)*16
 // + q16 and columns n0 + (wn*TN+j)*16 + 4 g4 .. + 3 of tile (i, j).
 template <class CF, class CS>
 __device__ __forceinline__ void store_tiles(const CS &cs, const floatx4 (&acc)[CF::TM][CF::TN], int64_t M, int N,
-                                            int64_t m0, int n0, int wm, int wn, int q16, int g4, int z) {
-  if constexpr (CS::kSide) {
+                                            int64_t m0, int n0, int wm, int wn, int q16, int g4, int z,
+                                            const SidePre<CF, CS> &sp) {
+  if constexpr (SidePre<CF, CS>::kOn) {
+#pragma unroll
+    for (int i = 0; i < CF::TM; ++i) {
+      const int64_t r = m0 + (wm * CF::TM + i) * 16 + q16;
+      if (r >= M) continue;
+#pragma unroll
+      for (int j = 0; j < CF::TN; ++j) {
+        const int n = n0 + (wn * CF::TN + j) * 16 + 4 * g4;
+        if (n + 3 < N) {
+          cs.store4s(r, n, z, acc[i][j], sp.cb[j], sp.em[i][j]);
+        } else {
+          for (int q = 0; q < 4; ++q)
+            if (n + q < N) cs(r, n + q, z, acc[i][j][q]);
+        }
+      }
+    }
+  } else if constexpr (CS::kSide) {
     // side inputs (bias, mask) of a chunk of tiles first, then its stores;
     // chunks of RG tile rows keep the prefetched values within ~12 tiles
     constexpr int RG = CF::TN >= 12 ? 1 : (12 / CF::TN < CF::TM ? 12 / CF::TN : CF::TM);
@@ -530,13 +576,23 @@ __global__ __launch_bounds__(256) void gemm_stream_kernel(AO ao, BO bo, CS cs, i
     }
     if (it + D < niter) issue(it + D);
   };
+  // Side inputs of the epilogue go out after the wait of the second-to-last
+  // stage (behind every DMA, so no stage wait has to cover them except the
+  // last, which waits for everything): their latency overlaps the last two
+  // stages instead of stalling the stores.
+  SidePre<CF, CS> sp;
+  const int side_it = niter >= 2 ? niter - 2 : 0;
   for (int it = 0; it < niter; ++it) {
     wait_issue(it);
+    if constexpr (SidePre<CF, CS>::kOn)
+      if (it == side_it) load_side<CF>(cs, sp, M, N, m0, n0, wm, wn, q16, g4, z);
     const char *sa = lds + (it % NS) * SB;
     const int nh = kend - (kbeg + it * SBK) > 16 ? 2 : 1;
     mma_stage<CF, F32>(aw, bw, sa, sa + AB, wm, wn, q16, g4, nh, acc);
   }
-  store_tiles<CF>(cs, acc, M, N, m0, n0, wm, wn, q16, g4, z);
+  if constexpr (SidePre<CF, CS>::kOn)
+    if (niter == 0) load_side<CF>(cs, sp, M, N, m0, n0, wm, wn, q16, g4, z);
+  store_tiles<CF>(cs, acc, M, N, m0, n0, wm, wn, q16, g4, z, sp);
 }
 
 template <int OP, class CF, bool F32, class AO, class BO, class CS>
