@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--voxels", type=int, default=None, help="override the voxel count (default: the workload's)")
     ap.add_argument("--chunk", type=int, default=1 << 17, help="LSC voxels per workspace pass")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--fp32-activations", action="store_true",
+                    help="BF16: keep the hidden LSC activations in float32 (default: bfloat16 storage)")
     ap.add_argument("--unfused-head", action="store_true",
                     help="run the loss head as SH2Signal, MSE and SH2Signal adjoint in three calls")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -266,7 +268,12 @@ def main():
     del x_h, clean_h
     S, K = plan.n_shells, plan.K
     f32 = dict(dtype=torch.float32, device=dev)
-    acts = [torch.empty((V, S, K), **f32)] + [torch.empty((V, ch[k + 1], p.K_out), **f32)
+    # BF16: the hidden activations and their gradients are stored in bfloat16
+    # (every contraction rounds them to bfloat16 on load, so no value changes)
+    half = prec == "bf16" and args.form == "folded" and not args.fp32_activations
+    act_dt = [torch.bfloat16 if half and 0 < k < len(layers) and (ch[k] * layers[k - 1][0].K_out) % 8 == 0
+              else torch.float32 for k in range(len(layers) + 1)]
+    acts = [torch.empty((V, S, K), **f32)] + [torch.empty((V, ch[k + 1], p.K_out), dtype=act_dt[k + 1], device=dev)
                                               for k, (p, _, _, _) in enumerate(layers)]
     grads = [torch.empty_like(a) for a in acts]
     fused_head = dl.sh2signal_mse_supported(plan) and not args.unfused_head
@@ -329,7 +336,8 @@ def main():
                    "b0_volumes": w.n_b0, "sh_order": w.sh_order, "lsc_channels": list(ch),
                    "kernel_sizes": list(w.kernel_sizes), "angular_distance_deg": 30.0, "lsc_form": form,
                    "precision": prec, "lsc_chunk_voxels": min(V, args.chunk),
-                   "loss_head": "fused" if fused_head else "unfused"},
+                   "loss_head": "fused" if fused_head else "unfused",
+                   "hidden_activation_storage": "bf16" if torch.bfloat16 in act_dt else "f32"},
     }
 
     if not args.no_kernel_timing:

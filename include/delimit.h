@@ -232,6 +232,33 @@ dlm_status dlm_lsc_bwd(const dlm_lsc_plan *plan, const float *a_in, int C, const
                        int64_t V, int relu_flags, dlm_lsc_form form, void *ws, size_t ws_bytes,
                        dlm_precision prec, void *stream);
 
+/* Storage of LSC activations in bfloat16 (bit flags, 0 = float32 as above).
+ * Every BF16 contraction rounds its operands to bfloat16 (RNE) as it loads
+ * them, so storing an activation rounded once instead changes no value the
+ * contraction sees (a positive float32 below 2^-133 that rounds to zero
+ * would flip a ReLU mask; nothing else differs) and halves its traffic:
+ * DLM_IO_IN_BF16:  a_in (and da_in) are bfloat16;
+ * DLM_IO_OUT_BF16: a_out (and da_out) are bfloat16.
+ * Needs DLM_BF16, the folded form, rows of a multiple of 8 entries (C*K_in
+ * for IN, O*K_out for OUT) and 16-byte aligned tensors (DLM_EINVAL
+ * otherwise).  In the backward, DLM_RELU_OUT is not available with these
+ * flags: the ReLU of a stacked layer is applied by the next layer's adjoint
+ * (DLM_RELU_IN). */
+typedef enum { DLM_IO_IN_BF16 = 1, DLM_IO_OUT_BF16 = 2 } dlm_io_flags;
+
+/* dlm_lsc_fwd with activation storage chosen by io_flags (void pointers to
+ * float32 or bfloat16 data as the flags say); io_flags = 0 is dlm_lsc_fwd. */
+dlm_status dlm_lsc_fwd_io(const dlm_lsc_plan *plan, const void *a_in, int C, const float *W,
+                          const float *bias, int O, void *a_out, int64_t V, int fuse_relu,
+                          int io_flags, dlm_lsc_form form, void *ws, size_t ws_bytes,
+                          dlm_precision prec, void *stream);
+/* dlm_lsc_bwd with activation storage chosen by io_flags; dW and dbias stay
+ * float32.  io_flags = 0 is dlm_lsc_bwd. */
+dlm_status dlm_lsc_bwd_io(const dlm_lsc_plan *plan, const void *a_in, int C, const float *W, int O,
+                          const void *a_out, const void *da_out, void *da_in, float *dW, float *dbias,
+                          int64_t V, int relu_flags, int io_flags, dlm_lsc_form form, void *ws,
+                          size_t ws_bytes, dlm_precision prec, void *stream);
+
 /* ------------------------------------------------------------------------
  * Training helpers (q-space loss, Sec. 1; optimiser)
  * ------------------------------------------------------------------------ */

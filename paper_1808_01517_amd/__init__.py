@@ -62,6 +62,15 @@ def _f32_dev(t: torch.Tensor, name: str) -> torch.Tensor:
     return t.contiguous()
 
 
+def _act_dev(t: torch.Tensor, name: str) -> torch.Tensor:
+    """An LSC activation: float32, or bfloat16 (BF16 folded form only)."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype not in (torch.float32, torch.bfloat16):
+        raise ValueError(f"{name} must be float32 or bfloat16 (got {t.dtype})")
+    return t.contiguous()
+
+
 def _c64(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
 
@@ -269,9 +278,12 @@ def sh2signal_bwd(plan: SHPlan, dx: torch.Tensor, out=None, precision="fp32") ->
 
 # -------------------------------------------------------------------- LSC
 def lsc_fwd(plan: LSCPlan, a_in: torch.Tensor, W: torch.Tensor, bias=None, relu: bool = False, out=None,
-            precision="fp32", workspace: Workspace | None = None, form=DEFAULT_FORM) -> torch.Tensor:
-    """a_in [V][C][K_in], W [O][C][T] (or [O][C][1][T]), bias [O] -> a_out [V][O][K_out]."""
-    a_in = _f32_dev(a_in, "a_in")
+            precision="fp32", workspace: Workspace | None = None, form=DEFAULT_FORM,
+            out_dtype=torch.float32) -> torch.Tensor:
+    """a_in [V][C][K_in], W [O][C][T] (or [O][C][1][T]), bias [O] -> a_out [V][O][K_out].
+    a_in and a_out (`out`, else `out_dtype`) may be bfloat16 with precision
+    "bf16" in the folded form: activations stored in bfloat16."""
+    a_in = _act_dev(a_in, "a_in")
     W = _f32_dev(W, "W").reshape(W.shape[0], W.shape[1], -1)
     V, Cin, Kin = a_in.shape
     O = W.shape[0]
@@ -284,9 +296,12 @@ def lsc_fwd(plan: LSCPlan, a_in: torch.Tensor, W: torch.Tensor, bias=None, relu:
     prec = precision_code(precision)
     ws = workspace or _default_ws(plan, Cin, O, V, prec, a_in.device, form)
     if out is None:
-        out = torch.empty((V, O, plan.K_out), dtype=torch.float32, device=a_in.device)
-    check(lib().dlm_lsc_fwd(plan.handle, _ptr(a_in), Cin, _ptr(W), _ptr(bias), O, _ptr(out), V, int(bool(relu)),
-                            form_code(form), ws.ptr(), ws.nbytes, prec, _stream(a_in)))
+        out = torch.empty((V, O, plan.K_out), dtype=out_dtype, device=a_in.device)
+    out = _act_dev(out, "out")
+    io = (_lib.DLM_IO_IN_BF16 if a_in.dtype == torch.bfloat16 else 0) | \
+        (_lib.DLM_IO_OUT_BF16 if out.dtype == torch.bfloat16 else 0)
+    check(lib().dlm_lsc_fwd_io(plan.handle, _ptr(a_in), Cin, _ptr(W), _ptr(bias), O, _ptr(out), V, int(bool(relu)),
+                               io, form_code(form), ws.ptr(), ws.nbytes, prec, _stream(a_in)))
     return out
 
 
@@ -297,12 +312,14 @@ def lsc_bwd(plan: LSCPlan, a_in: torch.Tensor, W: torch.Tensor, da_out: torch.Te
     relu: the forward fused a ReLU into a_out (da_out is masked by a_out > 0).
     relu_in: a_in is a ReLU output; da_in is returned masked by a_in > 0 (the
     gradient of the previous layer's pre-activation).
-    `outs` = (da_in, dW, dbias) preallocated float32 tensors (entries may be None)."""
-    a_in = _f32_dev(a_in, "a_in")
+    `outs` = (da_in, dW, dbias) preallocated tensors (entries may be None).
+    Activations may be bfloat16 (precision "bf16", folded form): da_in takes
+    a_in's dtype, a_out (when given) must have da_out's."""
+    a_in = _act_dev(a_in, "a_in")
     W = _f32_dev(W, "W").reshape(W.shape[0], W.shape[1], -1)
-    da_out = _f32_dev(da_out, "da_out")
+    da_out = _act_dev(da_out, "da_out")
     if relu:
-        a_out = _f32_dev(a_out, "a_out")
+        a_out = _act_dev(a_out, "a_out")
     V, Cin, _ = a_in.shape
     O = W.shape[0]
     prec = precision_code(precision)
@@ -315,9 +332,13 @@ def lsc_bwd(plan: LSCPlan, a_in: torch.Tensor, W: torch.Tensor, da_out: torch.Te
         if need_dW else None
     db = (o_db if o_db is not None else torch.empty((O,), dtype=torch.float32, device=dev)) if need_bias_grad else None
     flags = (_lib.DLM_RELU_OUT if relu else 0) | (_lib.DLM_RELU_IN if relu_in else 0)
-    check(lib().dlm_lsc_bwd(plan.handle, _ptr(a_in), Cin, _ptr(W), O, _ptr(a_out if relu else None), _ptr(da_out),
-                            _ptr(da_in), _ptr(dW), _ptr(db), V, flags, form_code(form), ws.ptr(),
-                            ws.nbytes, prec, _stream(a_in)))
+    if da_in is not None and da_in.dtype != a_in.dtype:
+        raise ValueError("da_in must have a_in's dtype")
+    io = (_lib.DLM_IO_IN_BF16 if a_in.dtype == torch.bfloat16 else 0) | \
+        (_lib.DLM_IO_OUT_BF16 if da_out.dtype == torch.bfloat16 else 0)
+    check(lib().dlm_lsc_bwd_io(plan.handle, _ptr(a_in), Cin, _ptr(W), O, _ptr(a_out if relu else None), _ptr(da_out),
+                               _ptr(da_in), _ptr(dW), _ptr(db), V, flags, io, form_code(form), ws.ptr(),
+                               ws.nbytes, prec, _stream(a_in)))
     return da_in, (dW if need_weight_grad else None), db
 
 

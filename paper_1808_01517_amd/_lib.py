@@ -12,6 +12,7 @@ DLM_OK, DLM_EINVAL, DLM_ESINGULAR, DLM_ENOMEM, DLM_EDEVICE, DLM_EWORKSPACE = ran
 DLM_FP32, DLM_BF16 = 0, 1
 DLM_LSC_RESAMPLE, DLM_LSC_FOLDED = 0, 1
 DLM_RELU_OUT, DLM_RELU_IN = 1, 2
+DLM_IO_IN_BF16, DLM_IO_OUT_BF16 = 1, 2
 
 _p = C.c_void_p
 _dp = C.POINTER(C.c_double)
@@ -45,6 +46,9 @@ SIGNATURES = {
     "dlm_lsc_workspace_bytes": (_st, [_p, _int, _int, _i64, _int, _int, C.POINTER(C.c_size_t)]),
     "dlm_lsc_fwd": (_st, [_p, _p, _int, _p, _p, _int, _p, _i64, _int, _int, _p, C.c_size_t, _int, _p]),
     "dlm_lsc_bwd": (_st, [_p, _p, _int, _p, _int, _p, _p, _p, _p, _p, _i64, _int, _int, _p, C.c_size_t, _int, _p]),
+    "dlm_lsc_fwd_io": (_st, [_p, _p, _int, _p, _p, _int, _p, _i64, _int, _int, _int, _p, C.c_size_t, _int, _p]),
+    "dlm_lsc_bwd_io": (_st, [_p, _p, _int, _p, _int, _p, _p, _p, _p, _p, _i64, _int, _int, _int, _p, C.c_size_t, _int,
+                             _p]),
     "dlm_mse_workspace_bytes": (C.c_size_t, [_i64]),
     "dlm_mse_fwd_bwd": (_st, [_p, _p, _i64, _p, _p, _p, C.c_size_t, _p]),
     "dlm_adam_step": (_st, [_p, _p, _p, _p, _i64, C.c_float, C.c_float, C.c_float, C.c_float, _i64, _p]),

@@ -92,7 +92,7 @@ def c4_batch(acq, index: int, V: int = 8192):
 # ------------------------------------------------------------ learned form
 
 def learned_setup(train_voxels=None, eval_voxels=262144, precision="bf16", form="folded", device="cuda:0",
-                  batch=8192, subset=15):
+                  batch=8192, subset=15, bf16_activations=False):
     w = dg.C5
     acq = dg.make_acquisition(w.config, w.shell_b, w.dirs_per_shell, w.perturb_deg, w.n_b0)
     idx = [dg.farthest_point_subset(d, subset) for d in acq.shell_dirs]
@@ -109,7 +109,8 @@ def learned_setup(train_voxels=None, eval_voxels=262144, precision="bf16", form=
               for k in range(1, len(ch) - 1)]
     weights = [dg.lsc_weights(w.config, k, ch[k], ch[k + 1], 1 + sum(w.kernel_sizes)) for k in range(len(ch) - 1)]
     net = LSCNetwork(plan_in, plan_out, dg.lsc_sampled_gradients(w), specs, w.kernel_sizes, w.angular_distance,
-                     w.lb_lambda, weights=weights, precision=precision, form=form, device=device, max_batch=batch)
+                     w.lb_lambda, weights=weights, precision=precision, form=form, device=device, max_batch=batch,
+                     bf16_activations=bf16_activations)
     # the plain method: order-4 fit from the same subset, evaluated on the full table
     fit_in = SHPlan(sub.bvecs, sub.bvals, w.sh_order_lsc_in, w.lb_lambda)
     fit_in0 = SHPlan(sub.bvecs, sub.bvals, w.sh_order_lsc_in, 0.0)

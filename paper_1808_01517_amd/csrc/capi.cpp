@@ -882,8 +882,8 @@ dlm_status fold_weights(const dlm_lsc_plan *p, int C, int O, const float *W, con
   return launched(launch_lsc_bias_vec(bias, p->dpm1.f32, O, p->K_out, w.bvec, stream));
 }
 
-dlm_status lsc_fwd_folded(const dlm_lsc_plan *p, const float *a_in, int C, const float *W, const float *bias, int O,
-                          float *a_out, int64_t V, int fuse_relu, void *ws, size_t ws_bytes, dlm_precision prec,
+dlm_status lsc_fwd_folded(const dlm_lsc_plan *p, const void *a_in, int C, const float *W, const float *bias, int O,
+                          void *a_out, int64_t V, int fuse_relu, int io, void *ws, size_t ws_bytes, dlm_precision prec,
                           void *stream) {
   if (ws_bytes < fold_ws_need(p, C, O))
     return fail(DLM_EWORKSPACE, "workspace of %zu bytes is below the %zu-byte minimum", ws_bytes, fold_ws_need(p, C, O));
@@ -892,12 +892,14 @@ dlm_status lsc_fwd_folded(const dlm_lsc_plan *p, const float *a_in, int C, const
   if (s != DLM_OK) return s;
   const int M = O * p->K_out, CK = C * p->K_in;
   TableGemm t;  // a_out[v][(o,k)] = sum_{(c,j)} Tw[(o,k)][(c,j)] a_in[v][(c,j)] + bias[o] (P_m 1)[k]
-  t.A = a_in;
+  if (io & DLM_IO_IN_BF16) t.Ah = static_cast<const uint16_t *>(a_in);
+  else t.A = static_cast<const float *>(a_in);
   t.lda = CK;
   t.Bf = w.Tw;
   t.Bh = w.Twh;
   t.ldb_f = t.ldb_h = int64_t(pad32(size_t(CK)));
-  t.C = a_out;
+  if (io & DLM_IO_OUT_BF16) t.Ch = static_cast<uint16_t *>(a_out);
+  else t.C = static_cast<float *>(a_out);
   t.ldc = M;
   t.bias_n = w.bvec;
   t.M = V;
@@ -905,12 +907,14 @@ dlm_status lsc_fwd_folded(const dlm_lsc_plan *p, const float *a_in, int C, const
   t.K = CK;
   t.relu = fuse_relu ? 1 : 0;
   t.op = kOpFoldFwd;
-  TimedScope ts("lsc_folded_fwd", stream, double(V) * (CK + double(M)) * 4.0, 2.0 * double(V) * M * CK);
+  TimedScope ts("lsc_folded_fwd", stream,
+                double(V) * (CK * ((io & DLM_IO_IN_BF16) ? 2.0 : 4.0) + double(M) * ((io & DLM_IO_OUT_BF16) ? 2.0 : 4.0)),
+                2.0 * double(V) * M * CK);
   return launched(launch_table_gemm(t, prec, stream));
 }
 
-dlm_status lsc_bwd_folded(const dlm_lsc_plan *p, const float *a_in, int C, const float *W, int O, const float *a_out,
-                          const float *da_out, float *da_in, float *dW, float *dbias, int64_t V, int relu_flags,
+dlm_status lsc_bwd_folded(const dlm_lsc_plan *p, const void *a_in, int C, const float *W, int O, const void *a_out,
+                          const void *da_out, void *da_in, float *dW, float *dbias, int64_t V, int relu_flags, int io,
                           void *ws, size_t ws_bytes, dlm_precision prec, void *stream) {
   if (ws_bytes < fold_ws_need(p, C, O))
     return fail(DLM_EWORKSPACE, "workspace of %zu bytes is below the %zu-byte minimum", ws_bytes, fold_ws_need(p, C, O));
@@ -918,25 +922,35 @@ dlm_status lsc_bwd_folded(const dlm_lsc_plan *p, const float *a_in, int C, const
   const int M = O * p->K_out, CK = C * p->K_in, N1 = CK + 1;
   if (dW && V > int64_t(0x7fffffff)) return fail(DLM_EINVAL, "V = %lld exceeds the 2^31-1 voxels of one call", (long long)V);
   dlm_status s;
-  const float *mask = (relu_flags & DLM_RELU_OUT) ? a_out : nullptr;
+  const bool in_h = io & DLM_IO_IN_BF16, out_h = io & DLM_IO_OUT_BF16;
+  // DLM_RELU_OUT with a bfloat16 a_out is rejected by the caller
+  const float *mask = (relu_flags & DLM_RELU_OUT) ? static_cast<const float *>(a_out) : nullptr;
   if (da_in && V > 0) {
     if ((s = fold_weights(p, C, O, W, nullptr, w, prec, stream)) != DLM_OK) return s;
     TableGemm t;  // da_in[v][(c,j)] = sum_{(o,k)} Tw[(o,k)][(c,j)] (da_out * [a_out > 0])[v][(o,k)]
-    t.A = da_out;
+    if (out_h) t.Ah = static_cast<const uint16_t *>(da_out);
+    else t.A = static_cast<const float *>(da_out);
     t.mask = mask;
     t.lda = M;
     t.Bf = w.TwT;
     t.Bh = w.TwTh;
     t.ldb_f = t.ldb_h = int64_t(pad32(size_t(M)));
-    t.C = da_in;
-    t.out_mask = (relu_flags & DLM_RELU_IN) ? a_in : nullptr;
+    if (in_h) {
+      t.Ch = static_cast<uint16_t *>(da_in);
+      t.out_mask_h = (relu_flags & DLM_RELU_IN) ? static_cast<const uint16_t *>(a_in) : nullptr;
+    } else {
+      t.C = static_cast<float *>(da_in);
+      t.out_mask = (relu_flags & DLM_RELU_IN) ? static_cast<const float *>(a_in) : nullptr;
+    }
     t.ldc = CK;
     t.M = V;
     t.N = CK;
     t.K = M;
     t.op = kOpFoldBwdData;
+    const double ob = out_h ? 2.0 : 4.0, ib = in_h ? 2.0 : 4.0;  // bytes per element
+    const bool omask = t.out_mask || t.out_mask_h;
     TimedScope ts("lsc_folded_bwd_data", stream,
-                  double(V) * (double(M) * (mask ? 2.0 : 1.0) + CK * (t.out_mask ? 2.0 : 1.0)) * 4.0,
+                  double(V) * (double(M) * (mask ? 2.0 : 1.0) * ob + CK * (omask ? 2.0 : 1.0) * ib),
                   2.0 * double(V) * M * CK);
     if ((s = launched(launch_table_gemm(t, prec, stream))) != DLM_OK) return s;
   }
@@ -945,10 +959,21 @@ dlm_status lsc_bwd_folded(const dlm_lsc_plan *p, const float *a_in, int C, const
     if (V > 0) {
       splits = fold_grad_splits(V, M, N1);
       if (splits > kFoldSplitMax) return fail(DLM_EINVAL, "internal: too many splits");
-      TimedScope ts("lsc_folded_grad", stream, double(V) * (double(M) * (mask ? 2.0 : 1.0) + CK) * 4.0,
+      TimedScope ts("lsc_folded_grad", stream,
+                    double(V) * (double(M) * (mask ? 2.0 : 1.0) * (out_h ? 2.0 : 4.0) + CK * (in_h ? 2.0 : 4.0)),
                     2.0 * double(V) * M * N1);
-      if ((s = launched(launch_lsc_fold_grad(da_out, mask, a_in, V, M, CK, splits, w.part, prec, stream))) != DLM_OK)
-        return s;
+      if (in_h || out_h) {
+        const int ks = fold_grad_split_len(V, splits);
+        s = launched(launch_stream_grad(out_h ? nullptr : static_cast<const float *>(da_out),
+                                        out_h ? static_cast<const uint16_t *>(da_out) : nullptr,
+                                        in_h ? nullptr : static_cast<const float *>(a_in),
+                                        in_h ? static_cast<const uint16_t *>(a_in) : nullptr, V, M, CK, splits, ks,
+                                        w.part, prec, stream));
+      } else {
+        s = launched(launch_lsc_fold_grad(static_cast<const float *>(da_out), mask, static_cast<const float *>(a_in), V,
+                                          M, CK, splits, w.part, prec, stream));
+      }
+      if (s != DLM_OK) return s;
     }
     {
       TimedScope ts("lsc_fold_reduce", stream, double(M) * N1 * 4.0, double(splits) * M * N1);
@@ -965,6 +990,64 @@ dlm_status lsc_bwd_folded(const dlm_lsc_plan *p, const float *a_in, int C, const
 
 }  // namespace
 
+namespace {
+bool aligned16p(const void *q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; }
+
+// bfloat16 activation storage: BF16 folded form, rows of a multiple of 8
+// entries, 16-byte aligned tensors
+dlm_status io_check(const dlm_lsc_plan *p, int C, int O, int io, dlm_lsc_form form, dlm_precision prec,
+                    const void *in0, const void *in1, const void *out0, const void *out1) {
+  if (io & ~(DLM_IO_IN_BF16 | DLM_IO_OUT_BF16)) return fail(DLM_EINVAL, "unknown io flags 0x%x", io);
+  if (io == 0) return DLM_OK;
+  if (prec != DLM_BF16 || form != DLM_LSC_FOLDED)
+    return fail(DLM_EINVAL, "bfloat16 activations need DLM_BF16 and the folded form");
+  if ((io & DLM_IO_IN_BF16) && ((C * p->K_in) % 8 != 0 || !aligned16p(in0) || !aligned16p(in1)))
+    return fail(DLM_EINVAL, "bfloat16 inputs need C*K_in (%d) a multiple of 8 and 16-byte aligned tensors",
+                C * p->K_in);
+  if ((io & DLM_IO_OUT_BF16) && ((O * p->K_out) % 8 != 0 || !aligned16p(out0) || !aligned16p(out1)))
+    return fail(DLM_EINVAL, "bfloat16 outputs need O*K_out (%d) a multiple of 8 and 16-byte aligned tensors",
+                O * p->K_out);
+  return DLM_OK;
+}
+}  // namespace
+
+dlm_status dlm_lsc_fwd_io(const dlm_lsc_plan *p, const void *a_in, int C, const float *W, const float *bias, int O,
+                          void *a_out, int64_t V, int fuse_relu, int io_flags, dlm_lsc_form form, void *ws,
+                          size_t ws_bytes, dlm_precision prec, void *stream) {
+  if (io_flags == 0)
+    return dlm_lsc_fwd(p, static_cast<const float *>(a_in), C, W, bias, O, static_cast<float *>(a_out), V, fuse_relu,
+                       form, ws, ws_bytes, prec, stream);
+  dlm_status s = lsc_check(p, C, O, V, prec);
+  if (s != DLM_OK) return s;
+  if ((s = io_check(p, C, O, io_flags, form, prec, a_in, nullptr, a_out, nullptr)) != DLM_OK) return s;
+  if (V == 0) return ok();
+  if (!a_in || !W || !a_out || !ws) return fail(DLM_EINVAL, "null device pointer");
+  s = lsc_fwd_folded(p, a_in, C, W, bias, O, a_out, V, fuse_relu, io_flags, ws, ws_bytes, prec, stream);
+  return s == DLM_OK ? ok() : s;
+}
+
+dlm_status dlm_lsc_bwd_io(const dlm_lsc_plan *p, const void *a_in, int C, const float *W, int O, const void *a_out,
+                          const void *da_out, void *da_in, float *dW, float *dbias, int64_t V, int relu_flags,
+                          int io_flags, dlm_lsc_form form, void *ws, size_t ws_bytes, dlm_precision prec,
+                          void *stream) {
+  if (io_flags == 0)
+    return dlm_lsc_bwd(p, static_cast<const float *>(a_in), C, W, O, static_cast<const float *>(a_out),
+                       static_cast<const float *>(da_out), static_cast<float *>(da_in), dW, dbias, V, relu_flags, form,
+                       ws, ws_bytes, prec, stream);
+  dlm_status s = lsc_check(p, C, O, V, prec);
+  if (s != DLM_OK) return s;
+  if ((s = io_check(p, C, O, io_flags, form, prec, a_in, da_in, a_out, da_out)) != DLM_OK) return s;
+  if (!ws) return fail(DLM_EINVAL, "workspace is NULL");
+  if (relu_flags & ~(DLM_RELU_OUT | DLM_RELU_IN)) return fail(DLM_EINVAL, "unknown relu flags 0x%x", relu_flags);
+  if (relu_flags & DLM_RELU_OUT)
+    return fail(DLM_EINVAL, "DLM_RELU_OUT with bfloat16 activations: mask in the next layer (DLM_RELU_IN) instead");
+  if (dbias && !dW) return fail(DLM_EINVAL, "dbias without dW is not supported");
+  if (V > 0 && (!a_in || !W || !da_out)) return fail(DLM_EINVAL, "null device pointer");
+  s = lsc_bwd_folded(p, a_in, C, W, O, a_out, da_out, da_in, dW, dbias, V, relu_flags, io_flags, ws, ws_bytes, prec,
+                     stream);
+  return s == DLM_OK ? ok() : s;
+}
+
 dlm_status dlm_lsc_fwd(const dlm_lsc_plan *p, const float *a_in, int C, const float *W, const float *bias, int O,
                        float *a_out, int64_t V, int fuse_relu, dlm_lsc_form form, void *ws, size_t ws_bytes,
                        dlm_precision prec, void *stream) {
@@ -974,7 +1057,7 @@ dlm_status dlm_lsc_fwd(const dlm_lsc_plan *p, const float *a_in, int C, const fl
   if (V == 0) return ok();
   if (!a_in || !W || !a_out || !ws) return fail(DLM_EINVAL, "null device pointer");
   if (form == DLM_LSC_FOLDED) {
-    s = lsc_fwd_folded(p, a_in, C, W, bias, O, a_out, V, fuse_relu, ws, ws_bytes, prec, stream);
+    s = lsc_fwd_folded(p, a_in, C, W, bias, O, a_out, V, fuse_relu, 0, ws, ws_bytes, prec, stream);
     return s == DLM_OK ? ok() : s;
   }
   const int64_t Vc = lsc_chunk(p, C, O, V, ws_bytes);
@@ -1044,7 +1127,8 @@ dlm_status dlm_lsc_bwd(const dlm_lsc_plan *p, const float *a_in, int C, const fl
   if (V > 0 && (!a_in || !W || !da_out)) return fail(DLM_EINVAL, "null device pointer");
   if (form == DLM_LSC_FOLDED) {
     if (V > 0 && !W) return fail(DLM_EINVAL, "null device pointer");
-    s = lsc_bwd_folded(p, a_in, C, W, O, a_out, da_out, da_in, dW, dbias, V, relu_flags, ws, ws_bytes, prec, stream);
+    s = lsc_bwd_folded(p, a_in, C, W, O, a_out, da_out, da_in, dW, dbias, V, relu_flags, 0, ws, ws_bytes, prec,
+                       stream);
     return s == DLM_OK ? ok() : s;
   }
   const int T = p->T, m = int(p->m);

@@ -78,6 +78,11 @@ struct TableGemm {
   int N = 0, K = 0, groups = 1;
   int relu = 0;
   KernelOp op = kOpS2shFwd;
+  // bfloat16 activations (BF16, streaming core only): A as Ah, C as Ch, the
+  // output mask as out_mask_h (with Ch); the float32 pointer is then null
+  const uint16_t *Ah = nullptr;
+  uint16_t *Ch = nullptr;
+  const uint16_t *out_mask_h = nullptr;
 };
 int launch_table_gemm(const TableGemm &g, dlm_precision prec, void *stream);
 
@@ -89,8 +94,11 @@ int launch_stream_table(const TableGemm &g, dlm_precision prec, void *stream);
 // Weight-gradient form of launch_lsc_fold_grad (no mask), ksplit a multiple of 32.
 // whether launch_stream_grad takes these sizes (ksplit: voxels per split)
 bool stream_grad_ok(int M, int CK, int ksplit);
-int launch_stream_grad(const float *g, const float *a, int64_t V, int M, int CK, int splits, int ksplit,
-                       float *partial, dlm_precision prec, void *stream);
+// g / a as float32, or (BF16 only) as bfloat16 gh / ah (M, CK multiples of 8,
+// 16-byte aligned); the other pointer of each pair is null.
+bool stream_grad_bf16_ok(const uint16_t *gh, const uint16_t *ah, int M, int CK);
+int launch_stream_grad(const float *g, const uint16_t *gh, const float *a, const uint16_t *ah, int64_t V, int M,
+                       int CK, int splits, int ksplit, float *partial, dlm_precision prec, void *stream);
 // Per-shell SH contraction, one wave per 16 voxels x one shell (groups
 // shells of equal size in one launch):
 //   C[v][g*c_gs + n] = sum_k A[v][g*a_gs + k] * Bt_g[n][k],  n < ncol, k < nred

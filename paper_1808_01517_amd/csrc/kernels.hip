@@ -497,6 +497,7 @@ static int table_gemm_op(const TableGemm &t, dlm_precision prec, hipStream_t st)
 
 int launch_table_gemm(const TableGemm &t, dlm_precision prec, void *stream) {
   if (stream_table_ok(t, prec)) return launch_stream_table(t, prec, stream);
+  if (t.Ah || t.Ch || t.out_mask_h) return -3;  // bfloat16 activations: streaming core only
   hipStream_t st = (hipStream_t)stream;
   switch (t.op) {
     case kOpS2shFwd: return table_gemm_op<kOpS2shFwd>(t, prec, st);
@@ -854,7 +855,7 @@ int launch_lsc_fold_grad(const float *da_out, const float *mask, const float *a_
   const int ks = split_len(V, splits);
   if ((V + ks - 1) / ks != splits) return -2;
   if (!mask && stream_grad_ok(M, CK, ks))
-    return launch_stream_grad(da_out, a_in, V, M, CK, splits, ks, partial, prec, stream);
+    return launch_stream_grad(da_out, nullptr, a_in, nullptr, V, M, CK, splits, ks, partial, prec, stream);
   hipStream_t st = (hipStream_t)stream;
   const Shape sh = grad_shape(M, N1);
   if (M >= N1) {

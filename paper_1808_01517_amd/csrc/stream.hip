@@ -278,6 +278,75 @@ struct SKh {
   }
 };
 
+// bfloat16 k-contiguous rows (activations stored in bfloat16): element
+// (r, k) at p[r * ldp + k], valid for r < rows, k < kend; ldp a multiple of 8
+// with 16-byte aligned rows and kend a multiple of 8, so a 16-byte chunk
+// (8 k) lies wholly inside or wholly beyond the range.  LDS as SKh.
+struct SKb : SKh {
+  template <int BR>
+  __device__ static int k_of(int s) {
+    const int r = s >> 2;
+    return 8 * ((s & 3) ^ ((r >> 1) & 3));
+  }
+};
+
+// bfloat16 row-contiguous (activations stored in bfloat16, reduced over
+// voxels): element (r, k) at p[k * ld + r], valid for r < rows, k < kend;
+// row `ones` (if >= 0) reads as 1 (set in registers, as in SRc).  A 16-byte
+// lane copies 8 consecutive rows of one k, so ld and rows are multiples of 8
+// and k-lines are 16-byte aligned.  LDS: [32][BR] bf16; the 8-row chunk c of
+// k-line k sits at chunk (c + 2 g(k)) mod (BR / 8), g(k) = (k >> 3) & 3, so
+// the four k of one fragment read (8 g4 + e, g4 = 0..3) land 32 bytes apart.
+struct SRb {
+  const uint16_t *p;
+  int64_t ld, rows, ones;
+  int orel = -1;
+  static constexpr int kUnit = 16;
+  template <int BR>
+  static constexpr int bytes() { return BR * SBK * 2; }
+  template <int BR>
+  static constexpr int slots() { return bytes<BR>() / kUnit; }
+  __device__ static int rot(int k) { return 2 * ((k >> 3) & 3); }
+  // rows beyond the matrix copy its last 8-row chunk (never stored)
+  __device__ int64_t clamp(int64_t gr) const { return gr < rows ? gr : rows - 8; }
+  __device__ int64_t rbase(int64_t r0) const { return r0 < rows - 8 ? r0 : rows - 8; }
+  __device__ const char *base(int64_t r0, int k0) const {
+    return reinterpret_cast<const char *>(p + (int64_t)k0 * ld + rbase(r0));
+  }
+  template <int BR>
+  __device__ uint32_t lane_off(int s, int64_t r0) const {
+    static_assert(BR % 16 == 0 && BR / 8 > 6, "row tile");
+    constexpr int NC = BR / 8;
+    const int k = s / NC;
+    int c = s - k * NC - rot(k);
+    if (c < 0) c += NC;
+    return (uint32_t)(((int64_t)k * ld + (clamp(r0 + 8 * c) - rbase(r0))) * 2);
+  }
+  template <int BR>
+  __device__ static int k_of(int s) { return s / (BR / 8); }
+  __device__ void bind(int64_t r0) {
+    const int64_t ro = ones - r0;
+    orel = ones >= 0 && ro >= 0 && ro < 1 << 20 ? (int)ro : -1;
+  }
+  __device__ bool ones_group(int rg) const { return orel >= 16 * rg && orel < 16 * rg + 16; }
+  template <int BR>
+  __device__ bf16x8 frag(const char *lds, int rg, int q16, int g4) const {
+    constexpr int NC = BR / 8;
+    const uint16_t *t = reinterpret_cast<const uint16_t *>(lds);
+    const int r = rg * 16 + q16, c = r >> 3, w = r & 7;
+    int pc = c + 2 * g4;  // rot(8 g4 + e) = 2 g4 for every e
+    if (pc >= NC) pc -= NC;
+    bf16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = __builtin_bit_cast(__bf16, t[(8 * g4 + e) * BR + pc * 8 + w]);
+    if (ones_group(rg) && q16 == orel - 16 * rg) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (__bf16)1.0f;
+    }
+    return v;
+  }
+};
+
 // ------------------------------------------------------------------ core
 template <int BM_, int BN_, int WM_, int WN_, int NS_>
 struct SCfg {
@@ -645,6 +714,52 @@ struct CRowSide {
   }
 };
 
+// The same with a bfloat16 output (RNE) and a bfloat16 mask: activations and
+// their gradients stored in bfloat16.  ldc a multiple of 4, 8-byte aligned rows.
+template <bool BIAS, bool MASK>
+struct CRowSideH {
+  static constexpr bool kSide = BIAS || MASK;
+  uint16_t *C;
+  int64_t ldc;
+  int relu;
+  const float *bias_n;
+  const uint16_t *omask;
+  __device__ static float widen(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
+  __device__ void operator()(int64_t r, int n, int, float v) const {
+    const int64_t o = r * ldc + n;
+    if constexpr (BIAS) v += bias_n[n];
+    if (relu) v = fmaxf(v, 0.0f);
+    if constexpr (MASK) v = widen(omask[o]) > 0.0f ? v : 0.0f;
+    C[o] = to_bf16_bits(v);
+  }
+  __device__ void store4(int64_t r, int n, int g, floatx4 v) const {
+    for (int q = 0; q < 4; ++q) (*this)(r, n + q, g, v[q]);
+  }
+  __device__ floatx4 colside(int n) const {
+    if constexpr (BIAS) return ld4(bias_n + n);
+    else return floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+  __device__ floatx4 elside(int64_t r, int n, int) const {
+    if constexpr (MASK) {
+      uint16_t h[4];
+      __builtin_memcpy(h, omask + r * ldc + n, 8);
+      return floatx4{widen(h[0]), widen(h[1]), widen(h[2]), widen(h[3])};
+    } else {
+      return floatx4{1.f, 1.f, 1.f, 1.f};
+    }
+  }
+  __device__ void store4s(int64_t r, int n, int, floatx4 v, floatx4 cb, floatx4 em) const {
+    uint16_t h[4];
+    for (int q = 0; q < 4; ++q) {
+      if constexpr (BIAS) v[q] += cb[q];
+      if (relu) v[q] = fmaxf(v[q], 0.0f);
+      if constexpr (MASK) v[q] = em[q] > 0.0f ? v[q] : 0.0f;
+      h[q] = to_bf16_bits(v[q]);
+    }
+    __builtin_memcpy(C + r * ldc + n, h, 8);
+  }
+};
+
 using SCfgWide = SCfg<128, 96, 2, 2, 3>;    // N = 1440, 2880: 15 / 30 tiles exactly
 // FP32 (two-stage ring): 64-row tiles hold four blocks per CU, which keeps the
 // matrix cores fed through the short (K = 135) reduction and the epilogue
@@ -666,6 +781,18 @@ int stream_table_c(AO ao, BO bo, CS cs, const TableGemm &t, hipStream_t st) {
 // the forward GEMM adds the folded bias; the input-gradient GEMM may mask
 template <int OP, bool F32, class AO, class BO>
 int stream_table(AO ao, BO bo, const TableGemm &t, hipStream_t st) {
+  if constexpr (!F32) {
+    if (t.Ch) {  // bfloat16 output (and mask)
+      if constexpr (OP == kOpFoldFwd) {
+        return stream_table_c<OP, F32>(ao, bo, CRowSideH<true, false>{t.Ch, t.ldc, t.relu, t.bias_n, nullptr}, t, st);
+      } else {
+        if (t.out_mask_h)
+          return stream_table_c<OP, F32>(ao, bo, CRowSideH<false, true>{t.Ch, t.ldc, t.relu, nullptr, t.out_mask_h},
+                                         t, st);
+        return stream_table_c<OP, F32>(ao, bo, CRowSideH<false, false>{t.Ch, t.ldc, t.relu, nullptr, nullptr}, t, st);
+      }
+    }
+  }
   if constexpr (OP == kOpFoldFwd) {
     return stream_table_c<OP, F32>(ao, bo, CRowSide<true, false>{t.C, t.ldc, t.relu, t.bias_n, nullptr}, t, st);
   } else {
@@ -684,6 +811,8 @@ int stream_table_b(AO ao, const TableGemm &t, hipStream_t st) {
 
 template <int OP, bool F32>
 int stream_table_op(const TableGemm &t, hipStream_t st) {
+  if constexpr (!F32)
+    if (t.Ah) return stream_table_b<OP, F32>(SKb{{t.Ah, t.lda, t.M}}, t, st);
   const bool vec = t.lda % 4 == 0 && t.K % 4 == 0 && aligned16(t.A);
   if (vec) return stream_table_b<OP, F32>(SKc<true>{t.A, t.lda, t.M}, t, st);
   return stream_table_b<OP, F32>(SKc<false>{t.A, t.lda, t.M}, t, st);
@@ -703,6 +832,12 @@ constexpr int64_t kMaxStreamLd = int64_t(1) << 22;
 
 bool stream_table_ok(const TableGemm &t, dlm_precision prec) {
   if (t.groups != 1 || t.mask != nullptr || (t.op != kOpFoldFwd && t.op != kOpFoldBwdData)) return false;
+  if (t.Ah || t.Ch || t.out_mask_h) {  // bfloat16 activations: BF16 only, 16-byte rows
+    if (prec != DLM_BF16) return false;
+    if (t.Ah && (t.A || t.lda % 8 != 0 || t.K % 8 != 0 || !aligned16(t.Ah))) return false;
+    if (t.Ch && (t.C || t.ldc % 8 != 0 || !aligned16(t.Ch))) return false;
+    if (t.out_mask_h && (!t.Ch || t.out_mask || !aligned16(t.out_mask_h))) return false;
+  }
   if (t.lda >= kMaxStreamLd || t.ldb_f >= kMaxStreamLd || t.ldb_h >= kMaxStreamLd) return false;
   if (t.op == kOpFoldFwd ? (t.bias_n == nullptr || t.out_mask != nullptr) : t.bias_n != nullptr) return false;
   if (prec == DLM_BF16)
@@ -724,35 +859,55 @@ int launch_stream_table(const TableGemm &t, dlm_precision prec, void *stream) {
 
 // dT[m][n] = sum_v g[v][m] * act[v][n] over voxel slices, act with a ones
 // column at n = CK (the bias term); the larger of M and CK + 1 on the row side.
+// g and act each come as float32 (g, a) or, in BF16, bfloat16 (gh, ah).
+struct GradArgs {
+  int64_t V;
+  int M, CK, splits, ksplit;
+  float *partial;
+  hipStream_t st;
+};
+
+template <bool F32, class GO, class AOp>
+static int grad_orient(GO go, AOp aop, const GradArgs &x) {
+  const int N1 = x.CK + 1;
+  if (x.M >= N1)
+    return stream_grad<F32>(go, aop, CPartial2<false>{x.partial, x.M, N1}, x.M, N1, x.V, x.splits, x.ksplit, x.st);
+  return stream_grad<F32>(aop, go, CPartial2<true>{x.partial, x.M, N1}, N1, x.M, x.V, x.splits, x.ksplit, x.st);
+}
+
+template <bool F32, class GO>
+static int grad_act(GO go, const float *a, const uint16_t *ah, const GradArgs &x) {
+  const int CK = x.CK;
+  if constexpr (!F32)
+    if (ah) return grad_orient<F32>(go, SRb{ah, CK, CK, CK}, x);
+  if (CK % 4 == 0 && aligned16(a)) return grad_orient<F32>(go, SRc<true>{a, CK, CK, CK}, x);
+  return grad_orient<F32>(go, SRc<false>{a, CK, CK, CK}, x);
+}
+
 template <bool F32>
-static int stream_grad_p(const float *g, const float *a, int64_t V, int M, int CK, int splits, int ksplit,
-                         float *partial, hipStream_t st) {
-  const int N1 = CK + 1;
-  const bool gv = M % 4 == 0 && aligned16(g), av = CK % 4 == 0 && aligned16(a);
-  if (M >= N1) {
-    const CPartial2<false> cs{partial, M, N1};
-    if (gv && av) return stream_grad<F32>(SRc<true>{g, M, M, -1}, SRc<true>{a, CK, CK, CK}, cs, M, N1, V, splits, ksplit, st);
-    if (gv) return stream_grad<F32>(SRc<true>{g, M, M, -1}, SRc<false>{a, CK, CK, CK}, cs, M, N1, V, splits, ksplit, st);
-    if (av) return stream_grad<F32>(SRc<false>{g, M, M, -1}, SRc<true>{a, CK, CK, CK}, cs, M, N1, V, splits, ksplit, st);
-    return stream_grad<F32>(SRc<false>{g, M, M, -1}, SRc<false>{a, CK, CK, CK}, cs, M, N1, V, splits, ksplit, st);
-  }
-  const CPartial2<true> cs{partial, M, N1};
-  if (gv && av) return stream_grad<F32>(SRc<true>{a, CK, CK, CK}, SRc<true>{g, M, M, -1}, cs, N1, M, V, splits, ksplit, st);
-  if (gv) return stream_grad<F32>(SRc<false>{a, CK, CK, CK}, SRc<true>{g, M, M, -1}, cs, N1, M, V, splits, ksplit, st);
-  if (av) return stream_grad<F32>(SRc<true>{a, CK, CK, CK}, SRc<false>{g, M, M, -1}, cs, N1, M, V, splits, ksplit, st);
-  return stream_grad<F32>(SRc<false>{a, CK, CK, CK}, SRc<false>{g, M, M, -1}, cs, N1, M, V, splits, ksplit, st);
+static int stream_grad_p(const float *g, const uint16_t *gh, const float *a, const uint16_t *ah, const GradArgs &x) {
+  const int M = x.M;
+  if constexpr (!F32)
+    if (gh) return grad_act<F32>(SRb{gh, M, M, -1}, a, ah, x);
+  if (M % 4 == 0 && aligned16(g)) return grad_act<F32>(SRc<true>{g, M, M, -1}, a, ah, x);
+  return grad_act<F32>(SRc<false>{g, M, M, -1}, a, ah, x);
 }
 
 bool stream_grad_ok(int M, int CK, int ksplit) {
   return ksplit % SBK == 0 && M < kMaxStreamLd && CK < kMaxStreamLd;
 }
 
-int launch_stream_grad(const float *g, const float *a, int64_t V, int M, int CK, int splits, int ksplit,
-                       float *partial, dlm_precision prec, void *stream) {
+bool stream_grad_bf16_ok(const uint16_t *gh, const uint16_t *ah, int M, int CK) {
+  return (!gh || (M % 8 == 0 && aligned16(gh))) && (!ah || (CK % 8 == 0 && aligned16(ah)));
+}
+
+int launch_stream_grad(const float *g, const uint16_t *gh, const float *a, const uint16_t *ah, int64_t V, int M,
+                       int CK, int splits, int ksplit, float *partial, dlm_precision prec, void *stream) {
   if (!stream_grad_ok(M, CK, ksplit)) return -2;
-  hipStream_t st = (hipStream_t)stream;
-  if (prec == DLM_BF16) return stream_grad_p<false>(g, a, V, M, CK, splits, ksplit, partial, st);
-  return stream_grad_p<true>(g, a, V, M, CK, splits, ksplit, partial, st);
+  if ((gh || ah) && (prec != DLM_BF16 || !stream_grad_bf16_ok(gh, ah, M, CK))) return -3;
+  const GradArgs x{V, M, CK, splits, ksplit, partial, (hipStream_t)stream};
+  if (prec == DLM_BF16) return stream_grad_p<false>(g, gh, a, ah, x);
+  return stream_grad_p<true>(g, nullptr, a, nullptr, x);
 }
 
 }  // namespace dlm

@@ -35,10 +35,14 @@ class LayerSpec:
 class LSCNetwork:
     def __init__(self, plan_in: SHPlan, plan_out: SHPlan, sampled_gradients, specs, kernel_sizes, angular_distance,
                  lb_lambda=0.006, weights=None, precision="fp32", form=DEFAULT_FORM, recompute=(), device="cuda:0",
-                 max_batch=8192):
+                 max_batch=8192, bf16_activations=False):
         self.plan_in, self.plan_out = plan_in, plan_out
         self.specs = list(specs)
         self.precision, self.form = precision, form
+        # hidden activations (and their gradients) stored in bfloat16: BF16
+        # folded form, rows of a multiple of 8 entries; the contractions round
+        # them to bfloat16 on load anyway
+        self.bf16_activations = bool(bf16_activations) and precision == "bf16" and form == "folded"
         self.recompute = set(int(k) for k in recompute)
         if any(k < 0 or k >= len(specs) - 1 for k in self.recompute):
             raise ValueError("only layers before the last can be recomputed")
@@ -74,15 +78,18 @@ class LSCNetwork:
         S, K = self.plan_in.n_shells, self.plan_in.K
         self.acts = [torch.empty((V, S, K), **f32)]
         shared = {}
+        n = len(self.specs)
         for k, (s, p) in enumerate(zip(self.specs, self.plans)):
             shape = (V, s.O, p.K_out)
+            half = self.bf16_activations and k < n - 1 and (s.O * p.K_out) % 8 == 0
+            dt = torch.bfloat16 if half else torch.float32
             if k in self.recompute:
-                if shape not in shared:
-                    shared[shape] = torch.empty(shape, **f32)
-                self.acts.append(shared[shape])
+                if (shape, dt) not in shared:
+                    shared[(shape, dt)] = torch.empty(shape, dtype=dt, device=self.dev)
+                self.acts.append(shared[(shape, dt)])
             else:
-                self.acts.append(torch.empty(shape, **f32))
-        self.grads = [torch.empty(a.shape, **f32) for a in self.acts]
+                self.acts.append(torch.empty(shape, dtype=dt, device=self.dev))
+        self.grads = [torch.empty(a.shape, dtype=a.dtype, device=self.dev) for a in self.acts]
         self.xhat = torch.empty((V, self.plan_out.n_dw), **f32)
         self.dxhat = torch.empty_like(self.xhat)
         self.loss = torch.empty((), **f32)

@@ -123,6 +123,64 @@ def test_lsc_backward_masks_input_gradient(prec, form, case):
     assert np.all(masked == 0.0)
 
 
+@pytest.mark.parametrize("case", [(3, 32, 8, 8, (8, 8), 90, 203), (32, 3, 8, 8, (8, 8), 90, 203),
+                                  (32, 64, 8, 8, (8, 8), 90, 171)])
+def test_lsc_bf16_activation_storage(case):
+    """BF16 folded form with activations (rows of a multiple of 8 entries)
+    stored in bfloat16.  The contractions see the same bfloat16 values as
+    with float32 storage of the same numbers, so the outputs equal the float32
+    path's rounded once, the weight gradients are identical, and both match
+    the oracle at the BF16 bound.  (32, 64): a 144-wide tile of the
+    activation operand starts at its ones column (CK = 1440)."""
+    C, O, L_in, L_out, ks, m, V = case
+    oplan, plan, W, b, a = _lsc_case(C, O, L_in, L_out, ks, m, V, 7)
+    in_half, out_half = (C * plan.K_in) % 8 == 0, (O * plan.K_out) % 8 == 0
+    half = torch.bfloat16
+    ag = cuda(a)
+    a_h = ag.to(half) if in_half else ag
+    a_f = a_h.float()  # the same numbers in float32 storage
+    a64 = a_f.double().cpu().numpy()
+    Wg, bg = cuda(W), cuda(b)
+    out_f = dl.lsc_fwd(plan, a_f, Wg, bg, relu=True, precision="bf16", form="folded")
+    out_h = dl.lsc_fwd(plan, a_h, Wg, bg, relu=True, precision="bf16", form="folded",
+                       out_dtype=half if out_half else torch.float32)
+    assert torch.equal(out_h, out_f.to(out_h.dtype))
+    out_ref, _ = olsc.lsc_forward(oplan, a64, W, b, True)
+    assert rel(out_h.float(), out_ref) <= TOL["bf16"]
+    da = cuda(np.random.default_rng(11).standard_normal((V, O, plan.K_out)))
+    da_h = da.to(half) if out_half else da
+    da_f = da_h.float()
+    gi_f, dW_f, db_f = dl.lsc_bwd(plan, a_f, Wg, da_f, relu_in=True, precision="bf16", form="folded")
+    gi_h, dW_h, db_h = dl.lsc_bwd(plan, a_h, Wg, da_h, relu_in=True, precision="bf16", form="folded")
+    assert gi_h.dtype == a_h.dtype
+    assert torch.equal(gi_h, gi_f.to(gi_h.dtype))
+    assert torch.equal(dW_h, dW_f) and torch.equal(db_h, db_f)
+    _, z = olsc.lsc_forward(oplan, a64, W, b, False)
+    da_ref, dW_ref, db_ref = olsc.lsc_backward(oplan, a64, W, z, da_f.double().cpu().numpy(), False)
+    errs = {"out": rel(out_h.float(), out_ref), "da_in": rel(gi_h.float(), da_ref * (a64 > 0)),
+            "dW": rel(dW_h, dW_ref), "db": rel(db_h, db_ref)}
+    print(f"[parity] lsc bf16 storage C={C} O={O}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    assert all(v <= TOL["bf16"] for v in errs.values()), errs
+
+
+def test_lsc_bf16_activation_storage_rejects_unsupported():
+    C, O, L_in, L_out, ks, m, V = (32, 3, 8, 8, (8, 8), 90, 64)
+    oplan, plan, W, b, a = _lsc_case(C, O, L_in, L_out, ks, m, V, 8)
+    a_h, Wg, bg = cuda(a).to(torch.bfloat16), cuda(W), cuda(b)
+    for kw in ({"precision": "fp32", "form": "folded"}, {"precision": "bf16", "form": "resample"}):
+        with pytest.raises(dl.DelimitError):
+            dl.lsc_fwd(plan, a_h, Wg, bg, **kw)
+    # C*K_in = 3 * 45 is not a multiple of 8
+    oplan3, plan3, W3, b3, a3 = _lsc_case(3, 32, 8, 8, (8, 8), 90, 64, 8)
+    with pytest.raises(dl.DelimitError):
+        dl.lsc_fwd(plan3, cuda(a3).to(torch.bfloat16), cuda(W3), cuda(b3), precision="bf16", form="folded")
+    # the ReLU of a bfloat16 output is applied by the next layer's adjoint
+    out = dl.lsc_fwd(plan3, cuda(a3), cuda(W3), cuda(b3), relu=True, precision="bf16", form="folded",
+                     out_dtype=torch.bfloat16)
+    with pytest.raises(dl.DelimitError):
+        dl.lsc_bwd(plan3, cuda(a3), cuda(W3), out, a_out=out, relu=True, precision="bf16", form="folded")
+
+
 def test_lsc_backward_rejects_unknown_relu_flags():
     C, O = 3, 4
     _, plan, W, b, a = _lsc_case(C, O, 4, 4, (6, 6), 30, 8, 14)

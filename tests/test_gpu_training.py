@@ -156,9 +156,10 @@ def test_checkpoint_resume_is_exact(tmp_path):
         assert torch.equal(full.W[k], resumed.W[k]) and torch.equal(full.b[k], resumed.b[k])
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_learned_network_gradients_vs_oracle(prec):
-    S = apps.learned_setup(precision=prec, batch=128)
+@pytest.mark.parametrize("prec,half", [("fp32", False), ("bf16", False), ("bf16", True)])
+def test_learned_network_gradients_vs_oracle(prec, half):
+    # half: hidden activations (64 x 45 per voxel) and their gradients stored in bfloat16
+    S = apps.learned_setup(precision=prec, batch=128, bf16_activations=half)
     net, acq, cols = S["net"], S["acq"], S["cols"]
     b = dg.stick_ball_batch(acq, 128, 3, 20.0, dg.rng_for(4, 2, 77))
     xs = f32(b.x[:, cols])
