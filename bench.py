@@ -181,7 +181,8 @@ def bench_c4(args):
     prec, form = args.precision, args.form
     w = dg.C4
     B = w.voxels
-    net, acq = apps.c4_network(prec, form, recompute=(0, 2), batch=B)
+    half = prec == "bf16" and form == "folded" and not args.fp32_activations
+    net, acq = apps.c4_network(prec, form, recompute=(0, 2), batch=B, bf16_activations=half)
     nb = 8
     batches = []
     for i in range(nb):
@@ -209,7 +210,8 @@ def bench_c4(args):
               "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
               "vs_baseline": None, "dtype": "f32" if prec == "fp32" else "bf16", "data": "synthetic",
               "config": {"workload": w.name, "batch": B, "lsc_channels": list(w.channels), "sh_order": w.sh_order,
-                         "distortion_deg": 3.0, "recompute_layers": [1, 3], "lsc_form": form, "precision": prec}}
+                         "distortion_deg": 3.0, "recompute_layers": [1, 3], "lsc_form": form, "precision": prec,
+                         "hidden_activation_storage": "bf16" if half else "f32"}}
     if not args.no_kernel_timing:
         import paper_1808_01517_amd as dl
         dl.timing_reset()

@@ -65,7 +65,8 @@ def nrmse(pred: torch.Tensor, ref: torch.Tensor) -> float:
 
 # --------------------------------------------------- differentiation workload
 
-def c4_network(precision="fp32", form="folded", recompute=(0, 2), device="cuda:0", weights=None, batch=8192):
+def c4_network(precision="fp32", form="folded", recompute=(0, 2), device="cuda:0", weights=None, batch=8192,
+               bf16_activations=False):
     w = dg.C4
     acq = dg.make_acquisition(w.config, w.shell_b, w.dirs_per_shell, w.perturb_deg, w.n_b0)
     plan = SHPlan(acq.bvecs, acq.bvals, w.sh_order, w.lb_lambda)
@@ -76,7 +77,7 @@ def c4_network(precision="fp32", form="folded", recompute=(0, 2), device="cuda:0
         weights = [dg.lsc_weights(w.config, k, ch[k], ch[k + 1], 1 + sum(w.kernel_sizes)) for k in range(len(ch) - 1)]
     net = LSCNetwork(plan, plan, dg.lsc_sampled_gradients(w), specs, w.kernel_sizes, w.angular_distance,
                      w.lb_lambda, weights=weights, precision=precision, form=form, recompute=recompute,
-                     device=device, max_batch=batch)
+                     device=device, max_batch=batch, bf16_activations=bf16_activations)
     return net, acq
 
 
@@ -133,10 +134,10 @@ def predict(setup, x_sub: torch.Tensor, batch=65536) -> torch.Tensor:
 
 
 def run_learned(train_voxels=1 << 22, eval_voxels=262144, epochs=8, lr=2e-3, batch=8192, precision="bf16",
-                form="folded", device="cuda:0", log=sys.stderr):
+                form="folded", device="cuda:0", log=sys.stderr, bf16_activations=True):
     dev = torch.device(device)
     t0 = time.perf_counter()
-    S = learned_setup(train_voxels, eval_voxels, precision, form, device, batch)
+    S = learned_setup(train_voxels, eval_voxels, precision, form, device, batch, bf16_activations=bf16_activations)
     w, acq, cols, net = S["w"], S["acq"], S["cols"], S["net"]
     xtr, ctr = _gen(acq, train_voxels, w, dg.STREAM_DATA)
     xev, cev = _gen(acq, eval_voxels, w, dg.STREAM_HELDOUT)

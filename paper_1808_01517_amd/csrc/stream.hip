@@ -760,11 +760,14 @@ struct CRowSideH {
   }
 };
 
-using SCfgWide = SCfg<128, 96, 2, 2, 3>;    // N = 1440, 2880: 15 / 30 tiles exactly
-// FP32 (two-stage ring): 64-row tiles hold four blocks per CU, which keeps the
-// matrix cores fed through the short (K = 135) reduction and the epilogue
+// BF16, N > 96 (N = 135/136, and 1440/2880 = 10/20 tiles exactly): one
+// configuration; for the K = 135 GEMMs it also amortises a block's fixed
+// cost (DMA offsets, first loads, epilogue) over 1.5x the output of 128 x 96
+using SCfgNarrow = SCfg<128, 144, 4, 1, 3>;
+// FP32, N > 144 (two-stage ring): 64-row tiles hold four blocks per CU, which
+// keeps the matrix cores fed through the short (K = 135) reduction and the
+// epilogue
 using SCfgWideF32 = SCfg<64, 96, 2, 2, 2>;
-using SCfgNarrow = SCfg<128, 144, 4, 1, 3>; // 96 < N <= 144 (N = 135, 136)
 using SCfgSmall = SCfg<128, 48, 4, 1, 3>;   // N <= 96
 // weight gradient: two float32 operands per stage (34 KB); a two-stage ring
 // keeps two blocks per CU
@@ -773,9 +776,9 @@ using SCfgGrad = SCfg<128, 144, 4, 1, 2>;
 template <int OP, bool F32, class AO, class BO, class CS>
 int stream_table_c(AO ao, BO bo, CS cs, const TableGemm &t, hipStream_t st) {
   if (t.N <= 96) return run_stream<OP, SCfgSmall, F32>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
-  if (t.N <= 144) return run_stream<OP, SCfgNarrow, F32>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
-  if constexpr (F32) return run_stream<OP, SCfgWideF32, F32>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
-  else return run_stream<OP, SCfgWide, F32>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
+  if constexpr (F32)
+    if (t.N > 144) return run_stream<OP, SCfgWideF32, F32>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
+  return run_stream<OP, SCfgNarrow, F32>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
 }
 
 // the forward GEMM adds the folded bias; the input-gradient GEMM may mask
