@@ -864,19 +864,26 @@ dlm_status dlm_lsc_workspace_bytes(const dlm_lsc_plan *p, int C, int O, int64_t 
 
 namespace {
 
+// The folded matrix for one use: T (forward, `transposed` false) or T^T
+// (input gradient), in the precision's storage only (float32 or bfloat16),
+// with its row padding zeroed.
 dlm_status fold_weights(const dlm_lsc_plan *p, int C, int O, const float *W, const float *bias, const FoldWs &w,
-                        dlm_precision prec, void *stream) {
+                        bool transposed, dlm_precision prec, void *stream) {
   const double KK = double(p->K_out) * p->K_in, M = double(O) * p->K_out, CK = double(C) * p->K_in;
+  const bool bf = prec == DLM_BF16;
   {
-    TimedScope ts("lsc_fold", stream, (double(O) * C * p->T + p->T * KK + 2.0 * M * CK) * 4.0,
+    TimedScope ts("lsc_fold", stream, (double(O) * C * p->T + p->T * KK) * 4.0 + M * CK * (bf ? 2.0 : 4.0),
                   2.0 * O * C * KK * p->T);
     const size_t M_ = size_t(O) * p->K_out, CK_ = size_t(C) * p->K_in;
-    // zero the padding (all four tables are contiguous in the workspace)
-    if (launch_zero(w.Tw, reinterpret_cast<char *>(w.TwTh) - reinterpret_cast<char *>(w.Tw) + CK_ * pad32(M_) * 2,
-                    stream) != 0)
+    const size_t esz = bf ? 2 : 4;
+    void *table = transposed ? (bf ? (void *)w.TwTh : (void *)w.TwT) : (bf ? (void *)w.Twh : (void *)w.Tw);
+    const size_t rows = transposed ? CK_ : M_, cols = transposed ? M_ : CK_;
+    if (launch_zero_cols(table, int64_t(rows), int64_t(cols * esz), int64_t(pad32(cols) * esz), stream) != 0)
       return launched(-1);
-    if (launch_lsc_fold(W, p->dQ.f32, C, O, p->T, p->K_in, p->K_out, w.Tw, w.TwT, prec == DLM_BF16 ? w.Twh : nullptr,
-                        prec == DLM_BF16 ? w.TwTh : nullptr, int64_t(pad32(CK_)), int64_t(pad32(M_)), stream) != 0)
+    float *Tw = !transposed && !bf ? w.Tw : nullptr, *TwT = transposed && !bf ? w.TwT : nullptr;
+    uint16_t *Twh = !transposed && bf ? w.Twh : nullptr, *TwTh = transposed && bf ? w.TwTh : nullptr;
+    if (launch_lsc_fold(W, p->dQ.f32, C, O, p->T, p->K_in, p->K_out, Tw, TwT, Twh, TwTh, int64_t(pad32(CK_)),
+                        int64_t(pad32(M_)), stream) != 0)
       return launched(-1);
   }
   return launched(launch_lsc_bias_vec(bias, p->dpm1.f32, O, p->K_out, w.bvec, stream));
@@ -888,7 +895,7 @@ dlm_status lsc_fwd_folded(const dlm_lsc_plan *p, const void *a_in, int C, const 
   if (ws_bytes < fold_ws_need(p, C, O))
     return fail(DLM_EWORKSPACE, "workspace of %zu bytes is below the %zu-byte minimum", ws_bytes, fold_ws_need(p, C, O));
   FoldWs w = fold_ws_carve(p, C, O, ws);
-  dlm_status s = fold_weights(p, C, O, W, bias, w, prec, stream);
+  dlm_status s = fold_weights(p, C, O, W, bias, w, false, prec, stream);
   if (s != DLM_OK) return s;
   const int M = O * p->K_out, CK = C * p->K_in;
   TableGemm t;  // a_out[v][(o,k)] = sum_{(c,j)} Tw[(o,k)][(c,j)] a_in[v][(c,j)] + bias[o] (P_m 1)[k]
@@ -926,7 +933,7 @@ dlm_status lsc_bwd_folded(const dlm_lsc_plan *p, const void *a_in, int C, const 
   // DLM_RELU_OUT with a bfloat16 a_out is rejected by the caller
   const float *mask = (relu_flags & DLM_RELU_OUT) ? static_cast<const float *>(a_out) : nullptr;
   if (da_in && V > 0) {
-    if ((s = fold_weights(p, C, O, W, nullptr, w, prec, stream)) != DLM_OK) return s;
+    if ((s = fold_weights(p, C, O, W, nullptr, w, true, prec, stream)) != DLM_OK) return s;
     TableGemm t;  // da_in[v][(c,j)] = sum_{(o,k)} Tw[(o,k)][(c,j)] (da_out * [a_out > 0])[v][(o,k)]
     if (out_h) t.Ah = static_cast<const uint16_t *>(da_out);
     else t.A = static_cast<const float *>(da_out);

@@ -158,6 +158,8 @@ int launch_sum_scaled(const float *partials, int64_t n, float *out, float scale,
 
 // fill `bytes` (a multiple of 4) at p with zeros
 int launch_zero(void *p, size_t bytes, void *stream);
+// zero bytes [c0_bytes, ld_bytes) of each of `rows` rows ld_bytes apart (even sizes)
+int launch_zero_cols(void *p, int64_t rows, int64_t c0_bytes, int64_t ld_bytes, void *stream);
 
 // y[v][o][i] = bias[o] + sum_{c,t} W[o][c][t] X[v][c][i*T+t]
 int launch_lsc_contract_fwd(const float *X, const float *W, const uint16_t *Wh, const float *bias, float *y,

@@ -725,8 +725,8 @@ struct CFold {
     const int k = n / Ki, j = n - k * Ki;
     const int64_t row = (int64_t)o * Ko + k, col = (int64_t)c * Ki + j;
     const int64_t a = row * ld + col, b = col * ldt + row;
-    Tw[a] = v;
-    TwT[b] = v;
+    if (Tw) Tw[a] = v;
+    if (TwT) TwT[b] = v;
     if (Twh) Twh[a] = to_bf16_bits(v);
     if (TwTh) TwTh[b] = to_bf16_bits(v);
   }
@@ -753,6 +753,24 @@ int launch_zero(void *p, size_t bytes, void *stream) {
   if (n == 0) return 0;
   hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
                      static_cast<uint32_t *>(p), n);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// zero bytes [c0, ld) of each of `rows` rows of ld bytes (c0, ld even)
+__global__ void zero_cols_kernel(uint16_t *p, int64_t rows, int64_t c0, int64_t ld) {
+  const int64_t w = (ld - c0) / 2;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * w) return;
+  const int64_t r = i / w;
+  p[(r * ld + c0) / 2 + (i - r * w)] = 0;
+}
+
+int launch_zero_cols(void *p, int64_t rows, int64_t c0_bytes, int64_t ld_bytes, void *stream) {
+  if (rows <= 0 || ld_bytes <= c0_bytes) return 0;
+  if ((c0_bytes | ld_bytes) & 1) return -3;
+  const int64_t n = rows * ((ld_bytes - c0_bytes) / 2);
+  hipLaunchKernelGGL(zero_cols_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     static_cast<uint16_t *>(p), rows, c0_bytes, ld_bytes);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
