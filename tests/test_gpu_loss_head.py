@@ -133,11 +133,15 @@ def test_loss_head_matches_unfused_composition(prec):
     assert rel(dc, dcu.double().cpu().numpy()) <= (1e-5 if prec == "fp32" else 1e-2)
 
 
-def test_loss_head_single_voxel():
+@pytest.mark.parametrize("V", [1, 17, 16 * 1400 + 5])
+def test_loss_head_batch_sizes(V):
+    """One voxel, one full 16-voxel tile plus one, and more per-wave partials
+    than one block sums (22 405 voxels x 3 shells = 4 203 waves > 4 096: the
+    two-pass sum)."""
     acq, L, _ = _case("c2")
     oplan = osh.SHPlan(acq.bvecs, acq.bvals, L, 0.006)
     plan = dl.SHPlan(acq.bvecs, acq.bvals, L, 0.006)
-    c, tgt = _inputs(acq, oplan, 1, 23)
+    c, tgt = _inputs(acq, oplan, V, 23)
     loss, dc, _ = dl.sh2signal_mse_fwd_bwd(plan, cuda(c), cuda(tgt))
     l_ref, dxh_ref = ostack.mse(osh.sh2signal(oplan, c), tgt)
     assert abs(loss.item() - l_ref) / l_ref <= TOL["fp32"]

@@ -351,3 +351,26 @@ def test_relative_mse():
                                        1e-3)
     assert abs(loss.item() - l_ref) / l_ref < 1e-5
     assert rel(dp, g_ref) < 1e-5
+
+
+def test_lsc_bf16_activation_storage_small_batches():
+    """bfloat16 storage at V = 0 (weight gradients zero), V = 1 and V = 33
+    (a ragged 16-row tile), and without an input gradient."""
+    C, O, L_in, L_out, ks, m = 32, 3, 8, 8, (8, 8), 90
+    oplan, plan, W, b, a = _lsc_case(C, O, L_in, L_out, ks, m, 33, 9)
+    Wg, bg = cuda(W), cuda(b)
+    empty = torch.zeros((0, C, plan.K_in), dtype=torch.bfloat16, device=DEV)
+    da0 = torch.zeros((0, O, plan.K_out), device=DEV)
+    _, dW0, db0 = dl.lsc_bwd(plan, empty, Wg, da0, precision="bf16", form="folded")
+    assert float(dW0.abs().max()) == 0.0 and float(db0.abs().max()) == 0.0
+    for V in (1, 33):
+        a_h = cuda(a[:V]).to(torch.bfloat16)
+        a64 = a_h.double().cpu().numpy()
+        out = dl.lsc_fwd(plan, a_h, Wg, bg, precision="bf16", form="folded")
+        out_ref, z = olsc.lsc_forward(oplan, a64, W, b, False)
+        assert rel(out, out_ref) <= TOL["bf16"]
+        da = cuda(np.random.default_rng(V).standard_normal((V, O, plan.K_out)))
+        none, dW, db = dl.lsc_bwd(plan, a_h, Wg, da, need_input_grad=False, precision="bf16", form="folded")
+        assert none is None
+        _, dW_ref, db_ref = olsc.lsc_backward(oplan, a64, W, z, da.double().cpu().numpy(), False)
+        assert rel(dW, dW_ref) <= TOL["bf16"] and rel(db, db_ref) <= TOL["bf16"]
