@@ -37,7 +37,7 @@ MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["c2", "c4"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c4", "sweep"], default="c2",
                     help="c2: three-shell stack fwd+bwd over 2^20 voxels (the headline); "
                          "c4: four-layer training step (fwd, MSE, bwd, Adam) on 8192-voxel batches")
     ap.add_argument("--steps", type=int, default=5)
@@ -228,13 +228,80 @@ def bench_c4(args):
     print(json.dumps(result), flush=True)
 
 
+def bench_sweep(args):
+    """Transform-only order sweep (the paper's Fig. 1 experiment re-done):
+    Signal2SH then SH2Signal on the three-shell table at SH orders 2..12,
+    450 000 synthetic voxels (about one brain scan), FP32 and BF16, next to
+    the FP64 oracle on the host cores.  One JSON line with a row per order."""
+    import torch
+
+    import datagen as dg
+    import paper_1808_01517_amd as dl
+    from oracle import sh as osh
+
+    dev = torch.device("cuda:0")
+    w = dg.C2
+    V = args.voxels or 450_000
+    acq, x_h, _ = make_data(w, V)
+    x = torch.from_numpy(x_h).to(dev)
+    rows = []
+    for L in (2, 4, 6, 8, 10, 12):
+        plan = dl.SHPlan(acq.bvecs, acq.bvals, L, w.lb_lambda)
+        c = torch.empty((V, plan.n_shells, plan.K), dtype=torch.float32, device=dev)
+        xr = torch.empty_like(x)
+        row = {"sh_order": L, "K": plan.K}
+        # oracle on the host: the same round trip in float64 on a bounded sample
+        n = min(V, 32768)
+        oplan = osh.SHPlan(acq.bvecs, acq.bvals, L, w.lb_lambda)
+        xs = x_h[:n].astype(np.float64)
+        t0 = time.perf_counter()
+        xo = osh.sh2signal(oplan, osh.signal2sh(oplan, xs))
+        tc = time.perf_counter() - t0
+        row["oracle_voxels_per_s"] = round(n / tc, 1)
+        for prec in ("fp32", "bf16"):
+            def rt():
+                dl.signal2sh_fwd(plan, x, out=c, precision=prec)
+                dl.sh2signal_fwd(plan, c, out=xr, precision=prec)
+            for _ in range(args.warmup):
+                rt()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                rt()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            dl.timing_reset()
+            dl.timing_enable(True)
+            rt()
+            torch.cuda.synchronize()
+            dl.timing_enable(False)
+            rep = dl.timing_report()
+            nbytes = sum(v[2] for v in rep.values())
+            err = float(np.linalg.norm(xr[:n].double().cpu().numpy() - xo) / np.linalg.norm(xo))
+            row[prec] = {"ms": round(ms, 4), "voxels_per_s": round(V / (ms / 1e3), 1),
+                         "hbm_frac": round(nbytes / (ms / 1e3) / (HBM_PEAK_GBS * 1e9), 4),
+                         "rel_err_vs_oracle": err}
+        rows.append(row)
+        print(f"[sweep] L={L} K={plan.K}: fp32 {row['fp32']['ms']:.3f} ms, bf16 {row['bf16']['ms']:.3f} ms, "
+              f"oracle {row['oracle_voxels_per_s']:.0f} voxels/s", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "voxels/s Signal2SH + SH2Signal round trip by SH order", "unit": "voxels/s",
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "data": "synthetic",
+                      "config": {"workload": "order-sweep-3shell-90dir", "voxels": V, "shells": 3,
+                                 "dirs_per_shell": 90, "lb_lambda": w.lb_lambda,
+                                 "oracle_sample_voxels": min(V, 32768),
+                                 "oracle_threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))},
+                      "rows": rows}), flush=True)
+
+
 def main():
     args = parse()
-    if args.workload == "c4":
+    if args.workload in ("c4", "sweep"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
-        bench_c4(args)
+        (bench_c4 if args.workload == "c4" else bench_sweep)(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the layers are per-voxel and this build "

@@ -67,6 +67,34 @@ def test_sh_transforms(prec, which, c1_acq, c2_acq):
     assert rel(dcc, osh.sh2signal_adjoint(oplan, dxx.astype(np.float32))) <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("L", [2, 6, 10, 12])
+def test_sh_transforms_across_orders(prec, L, c2_acq):
+    """The order sweep's transforms: K = 6 .. 91 on the three-shell table
+    (orders 10 and 12 exceed the per-shell kernel's K <= 64 and run on the
+    register-staged core; at order 12, K = 91 > 90 directions per shell,
+    determined by the Laplace-Beltrami penalty)."""
+    acq, V = c2_acq, 1000 + 13
+    oplan = osh.SHPlan(acq.bvecs, acq.bvals, L, 0.006)
+    plan = dl.SHPlan(acq.bvecs, acq.bvals, L, 0.006)
+    assert plan.K == oplan.K == (L + 1) * (L + 2) // 2
+    x = dg.stick_ball_batch(acq, V, 3, 20.0, dg.rng_for(12, 2, L)).x
+    c = dl.signal2sh_fwd(plan, cuda(x), precision=prec)
+    c_ref = osh.signal2sh(oplan, x.astype(np.float32).astype(np.float64))
+    xr = dl.sh2signal_fwd(plan, c, precision=prec)
+    xr_ref = osh.sh2signal(oplan, c.double().cpu().numpy())
+    rng = np.random.default_rng(L)
+    dx = rng.standard_normal(x.shape)
+    dc = dl.sh2signal_bwd(plan, cuda(dx), precision=prec)
+    dcc = rng.standard_normal(c_ref.shape)
+    dxx = dl.signal2sh_bwd(plan, cuda(dcc), precision=prec)
+    errs = {"c": rel(c, c_ref), "x": rel(xr, xr_ref),
+            "dc": rel(dc, osh.sh2signal_adjoint(oplan, dx.astype(np.float32))),
+            "dx": rel(dxx, osh.signal2sh_adjoint(oplan, dcc.astype(np.float32)))}
+    print(f"[parity] sh order {L} {prec}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    assert all(v <= TOL[prec] for v in errs.values()), errs
+
+
 def _lsc_case(C, O, L_in, L_out, ks, m_dirs, V, seed):
     g = dg.fibonacci_hemisphere(m_dirs)
     oplan = olsc.LSCPlan(g, L_in, L_out, ks, np.deg2rad(30), 0.006)
