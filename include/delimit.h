@@ -9,8 +9,9 @@
  * - Plain C: no C++ or torch types.  Voxel counts are int64_t.  A stream
  *   is a hipStream_t passed as void* (NULL = the default stream).
  * - Pointers documented "device" must point to device memory of the current
- *   HIP device; "host" pointers are ordinary CPU memory.  All device data at
- *   the ABI is row-major float32; the caller owns every activation,
+ *   HIP device; "host" pointers are ordinary CPU memory.  Device data at the
+ *   ABI is row-major float32, except LSC activations passed to the _io
+ *   calls as bfloat16 (dlm_io_flags); the caller owns every activation,
  *   gradient, weight and workspace buffer.  Plans own their device tables.
  * - Compute calls are asynchronous on the given stream and never allocate;
  *   they validate every argument on the host before any launch and return a

@@ -1,8 +1,12 @@
-// HIP kernels for gfx950 (MI355X): every contraction of the DELIMIT layers
-// runs through one matrix-core GEMM core whose operand addressing is a
-// policy type, so the SH transforms (Sec. 2.2), the LSC neighbourhood
-// resampling, the cyclic-kernel row dot and the refit (Sec. 2.3) and all
-// their adjoints share the same tiled MFMA pipeline:
+// HIP kernels for gfx950 (MI355X): the register-staged matrix-core GEMM
+// core, whose operand addressing is a policy type, and the small kernels
+// (fold/unfold of the kernel tensor, losses, Adam, reductions).  The SH
+// reductions over a shell's directions (Sec. 2.2), the LSC neighbourhood
+// resampling, cyclic-kernel row dot and refit in the paper's order
+// (Sec. 2.3), the fold of the kernel tensor and the masked LSC GEMMs share
+// this tiled MFMA pipeline (the folded LSC GEMMs run on the streaming core,
+// stream.hip; the per-shell SH contractions over the coefficients and the
+// loss head on shell.hip):
 //
 //   C[r][n] = sum_k A(r, k) * B(n, k)
 //

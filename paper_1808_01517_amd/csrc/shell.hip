@@ -1,5 +1,6 @@
 // Per-shell SH contractions (Sec. 2.2: Signal2SH c = P_s x, SH2Signal
-// x = B_s c, and their adjoints) for one MI355X.
+// x = B_s c, and their adjoints) for one MI355X, and the q-space loss head
+// that fuses SH2Signal, the MSE and the SH2Signal adjoint (sh2s_mse_kernel).
 //
 // Each is, per voxel v and shell g,
 //   C[v][g*c_gs + n] = sum_k A[v][g*a_gs + k] * Bt_g[n][k],   n < ncol, k < nred,

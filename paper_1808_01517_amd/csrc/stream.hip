@@ -12,7 +12,8 @@
 //   global_load_lds_dword / _dwordx4 (no register staging), through a ring of
 //   NS stages, so NS-1 slices of 32 k are in flight while one is multiplied.
 // * Float32 operands stay float32 in LDS and are rounded to bfloat16 (RNE)
-//   when a wave reads its MFMA fragment; bfloat16 tables are copied as is.
+//   when a wave reads its MFMA fragment; bfloat16 tables and activations
+//   stored in bfloat16 are copied as is (the same values either way).
 //   A stage wholly inside the reduction range copies from one wave-uniform
 //   base address plus per-lane 32-bit offsets computed once per block, so
 //   the loop spends a scalar add and one instruction per copy.  In the one
@@ -28,6 +29,9 @@
 // * Waits are explicit: s_waitcnt vmcnt(n) for the slice about to be used,
 //   then a barrier.  A slot is refilled only after the barrier that follows
 //   its last read by every wave.
+// * The epilogue's side inputs (bias, ReLU mask) are loaded behind the last
+//   DMA, after the second-to-last stage's wait, when they fit in registers;
+//   only the last stage's wait then covers them.
 //
 // MFMA, B fragment first, so each accumulator is the transposed 16 x 16
 // tile (a lane holds four consecutive output columns of one row), the same

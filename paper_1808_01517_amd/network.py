@@ -10,6 +10,11 @@ share a single buffer, which later layers overwrite; the backward pass
 recomputes the output from the stored layer input right before the next
 layer's adjoint consumes it.  The kernels are deterministic, so gradients
 are bitwise identical to the run that keeps every activation.
+
+When the output table allows it, the loss step runs as one fused pass
+(SH2Signal, MSE and the SH2Signal adjoint).  With `bf16_activations` in the
+BF16 folded form, hidden activations and their gradients are stored in
+bfloat16, which leaves every value the contractions see unchanged.
 """
 from __future__ import annotations
 
