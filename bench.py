@@ -52,6 +52,10 @@ def parse():
                     help="BF16: keep the hidden LSC activations in float32 (default: bfloat16 storage)")
     ap.add_argument("--unfused-head", action="store_true",
                     help="run the loss head as SH2Signal, MSE and SH2Signal adjoint in three calls")
+    ap.add_argument("--relu-mask", choices=["auto", "bits", "activation"], default="auto",
+                    help="source of the hidden ReLU's backward mask: one bit per element written by the forward, or "
+                         "the stored activation (auto: bits in BF16, where the step is memory-bound; the activation "
+                         "in FP32, where the extra epilogue work costs more than the saved reads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--with-copy-calibration", action="store_true",
@@ -345,6 +349,11 @@ def main():
     acts = [torch.empty((V, S, K), **f32)] + [torch.empty((V, ch[k + 1], p.K_out), dtype=act_dt[k + 1], device=dev)
                                               for k, (p, _, _, _) in enumerate(layers)]
     grads = [torch.empty_like(a) for a in acts]
+    # a hidden ReLU's backward mask travels as one bit per element
+    use_bits = args.relu_mask == "bits" or (args.relu_mask == "auto" and prec == "bf16")
+    bits = [dl.relu_bits_like(acts[k + 1]) if args.form == "folded" and relu and use_bits
+            and (ch[k + 1] * p.K_out) % 16 == 0 else None for k, (p, _, _, relu) in enumerate(layers)]
+    bits = [None] + bits
     fused_head = dl.sh2signal_mse_supported(plan) and not args.unfused_head
     xhat = None if fused_head else torch.empty_like(x)
     dxhat = None if fused_head else torch.empty_like(x)
@@ -362,7 +371,8 @@ def main():
     def step():
         dl.signal2sh_fwd(plan, x, out=acts[0], precision=prec)
         for k, (p, Wk, bk, relu) in enumerate(layers):
-            dl.lsc_fwd(p, acts[k], Wk, bk, relu=relu, out=acts[k + 1], precision=prec, workspace=ws, form=form)
+            dl.lsc_fwd(p, acts[k], Wk, bk, relu=relu, out=acts[k + 1], precision=prec, workspace=ws, form=form,
+                       relu_bits=bits[k + 1])
         if fused_head:  # x^ and its gradient never go through HBM
             dl.sh2signal_mse_fwd_bwd(plan, acts[-1], tgt, precision=prec, outs=(loss, grads[-1], head_ws))
         else:
@@ -375,7 +385,8 @@ def main():
             relu_in = k > 0 and layers[k - 1][3]
             relu_out = relu and k == len(layers) - 1
             dl.lsc_bwd(p, acts[k], Wk, grads[k + 1], a_out=acts[k + 1], relu=relu_out, relu_in=relu_in,
-                       precision=prec, workspace=ws, outs=(grads[k], dWs[k], dbs[k]), form=form)
+                       precision=prec, workspace=ws, outs=(grads[k], dWs[k], dbs[k]), form=form,
+                       relu_bits=bits[k] if relu_in else None)
         dl.signal2sh_bwd(plan, grads[0], out=dx, precision=prec)
 
     for _ in range(args.warmup):
@@ -406,7 +417,8 @@ def main():
                    "kernel_sizes": list(w.kernel_sizes), "angular_distance_deg": 30.0, "lsc_form": form,
                    "precision": prec, "lsc_chunk_voxels": min(V, args.chunk),
                    "loss_head": "fused" if fused_head else "unfused",
-                   "hidden_activation_storage": "bf16" if torch.bfloat16 in act_dt else "f32"},
+                   "hidden_activation_storage": "bf16" if torch.bfloat16 in act_dt else "f32",
+                   "relu_backward_mask": "bits" if any(b is not None for b in bits) else "activation"},
     }
 
     if not args.no_kernel_timing:

@@ -247,18 +247,33 @@ dlm_status dlm_lsc_bwd(const dlm_lsc_plan *plan, const float *a_in, int C, const
  * (DLM_RELU_IN). */
 typedef enum { DLM_IO_IN_BF16 = 1, DLM_IO_OUT_BF16 = 2 } dlm_io_flags;
 
+/* ReLU bits: a stacked layer's ReLU needs, in the backward, only the sign
+ * pattern of its output, one bit per element instead of the 2- or 4-byte
+ * activation.  relu_bits is a device array [V][N/16] of uint16, N the row
+ * length (O*K_out in the forward, C*K_in in the backward, a multiple of 16);
+ * bit (n mod 16) of word [v][n/16] is 1 iff the stored activation a[v][n] is
+ * > 0 (after its bfloat16 rounding when stored in bfloat16).  Caller-owned,
+ * written whole by the forward, read by the backward; NULL = not used.
+ * Needs the folded form (DLM_EINVAL otherwise). */
+
 /* dlm_lsc_fwd with activation storage chosen by io_flags (void pointers to
- * float32 or bfloat16 data as the flags say); io_flags = 0 is dlm_lsc_fwd. */
+ * float32 or bfloat16 data as the flags say); io_flags = 0 is dlm_lsc_fwd.
+ * relu_bits (NULL or as above, needs fuse_relu) receives the output's ReLU
+ * bits beside a_out. */
 dlm_status dlm_lsc_fwd_io(const dlm_lsc_plan *plan, const void *a_in, int C, const float *W,
                           const float *bias, int O, void *a_out, int64_t V, int fuse_relu,
-                          int io_flags, dlm_lsc_form form, void *ws, size_t ws_bytes,
-                          dlm_precision prec, void *stream);
+                          int io_flags, uint16_t *relu_bits, dlm_lsc_form form, void *ws,
+                          size_t ws_bytes, dlm_precision prec, void *stream);
 /* dlm_lsc_bwd with activation storage chosen by io_flags; dW and dbias stay
- * float32.  io_flags = 0 is dlm_lsc_bwd. */
+ * float32.  io_flags = 0 and relu_bits = NULL is dlm_lsc_bwd.  relu_bits
+ * (NULL or as above, needs DLM_RELU_IN, excludes DLM_RELU_OUT) replaces
+ * a_in as the source of the DLM_RELU_IN mask, with identical results; a_in
+ * is still read for dW. */
 dlm_status dlm_lsc_bwd_io(const dlm_lsc_plan *plan, const void *a_in, int C, const float *W, int O,
                           const void *a_out, const void *da_out, void *da_in, float *dW, float *dbias,
-                          int64_t V, int relu_flags, int io_flags, dlm_lsc_form form, void *ws,
-                          size_t ws_bytes, dlm_precision prec, void *stream);
+                          int64_t V, int relu_flags, int io_flags, const uint16_t *relu_bits,
+                          dlm_lsc_form form, void *ws, size_t ws_bytes, dlm_precision prec,
+                          void *stream);
 
 /* ------------------------------------------------------------------------
  * Training helpers (q-space loss, Sec. 1; optimiser)

@@ -277,12 +277,31 @@ def sh2signal_bwd(plan: SHPlan, dx: torch.Tensor, out=None, precision="fp32") ->
 
 
 # -------------------------------------------------------------------- LSC
+def relu_bits_like(a: torch.Tensor) -> torch.Tensor:
+    """An int16 [V][N/16] buffer for the ReLU bits of activations a [V][...]
+    (N entries per row, a multiple of 16)."""
+    n = a[0].numel() if a.shape[0] else int(np.prod(a.shape[1:]))
+    if n % 16:
+        raise ValueError(f"ReLU bits need rows of a multiple of 16 entries, got {n}")
+    return torch.empty((a.shape[0], n // 16), dtype=torch.int16, device=a.device)
+
+
+def _bits_dev(bits, V, n, name):
+    if bits is None:
+        return None
+    if bits.dtype != torch.int16 or not bits.is_cuda or not bits.is_contiguous() or tuple(bits.shape) != (V, n // 16):
+        raise ValueError(f"{name} must be a contiguous int16 device tensor of shape ({V}, {n // 16})")
+    return bits
+
+
 def lsc_fwd(plan: LSCPlan, a_in: torch.Tensor, W: torch.Tensor, bias=None, relu: bool = False, out=None,
             precision="fp32", workspace: Workspace | None = None, form=DEFAULT_FORM,
-            out_dtype=torch.float32) -> torch.Tensor:
+            out_dtype=torch.float32, relu_bits=None) -> torch.Tensor:
     """a_in [V][C][K_in], W [O][C][T] (or [O][C][1][T]), bias [O] -> a_out [V][O][K_out].
     a_in and a_out (`out`, else `out_dtype`) may be bfloat16 with precision
-    "bf16" in the folded form: activations stored in bfloat16."""
+    "bf16" in the folded form: activations stored in bfloat16.
+    relu_bits (with relu, folded form): an int16 [V][O*K_out/16] tensor that
+    receives bit n%16 of word n/16 = [a_out[v].flat[n] > 0]."""
     a_in = _act_dev(a_in, "a_in")
     W = _f32_dev(W, "W").reshape(W.shape[0], W.shape[1], -1)
     V, Cin, Kin = a_in.shape
@@ -300,21 +319,24 @@ def lsc_fwd(plan: LSCPlan, a_in: torch.Tensor, W: torch.Tensor, bias=None, relu:
     out = _act_dev(out, "out")
     io = (_lib.DLM_IO_IN_BF16 if a_in.dtype == torch.bfloat16 else 0) | \
         (_lib.DLM_IO_OUT_BF16 if out.dtype == torch.bfloat16 else 0)
+    relu_bits = _bits_dev(relu_bits, V, O * plan.K_out, "relu_bits")
     check(lib().dlm_lsc_fwd_io(plan.handle, _ptr(a_in), Cin, _ptr(W), _ptr(bias), O, _ptr(out), V, int(bool(relu)),
-                               io, form_code(form), ws.ptr(), ws.nbytes, prec, _stream(a_in)))
+                               io, _ptr(relu_bits), form_code(form), ws.ptr(), ws.nbytes, prec, _stream(a_in)))
     return out
 
 
 def lsc_bwd(plan: LSCPlan, a_in: torch.Tensor, W: torch.Tensor, da_out: torch.Tensor, a_out=None, relu=False,
             need_input_grad=True, need_weight_grad=True, need_bias_grad=True, precision="fp32",
-            workspace: Workspace | None = None, outs=None, form=DEFAULT_FORM, relu_in=False):
+            workspace: Workspace | None = None, outs=None, form=DEFAULT_FORM, relu_in=False, relu_bits=None):
     """Returns (da_in or None, dW [O][C][T] or None, dbias [O] or None).
     relu: the forward fused a ReLU into a_out (da_out is masked by a_out > 0).
     relu_in: a_in is a ReLU output; da_in is returned masked by a_in > 0 (the
     gradient of the previous layer's pre-activation).
     `outs` = (da_in, dW, dbias) preallocated tensors (entries may be None).
     Activations may be bfloat16 (precision "bf16", folded form): da_in takes
-    a_in's dtype, a_out (when given) must have da_out's."""
+    a_in's dtype, a_out (when given) must have da_out's.
+    relu_bits (with relu_in, folded form): the ReLU bits lsc_fwd wrote for
+    a_in; the relu_in mask is read from them instead of a_in (same result)."""
     a_in = _act_dev(a_in, "a_in")
     W = _f32_dev(W, "W").reshape(W.shape[0], W.shape[1], -1)
     da_out = _act_dev(da_out, "da_out")
@@ -336,9 +358,10 @@ def lsc_bwd(plan: LSCPlan, a_in: torch.Tensor, W: torch.Tensor, da_out: torch.Te
         raise ValueError("da_in must have a_in's dtype")
     io = (_lib.DLM_IO_IN_BF16 if a_in.dtype == torch.bfloat16 else 0) | \
         (_lib.DLM_IO_OUT_BF16 if da_out.dtype == torch.bfloat16 else 0)
+    relu_bits = _bits_dev(relu_bits, V, Cin * plan.K_in, "relu_bits")
     check(lib().dlm_lsc_bwd_io(plan.handle, _ptr(a_in), Cin, _ptr(W), O, _ptr(a_out if relu else None), _ptr(da_out),
-                               _ptr(da_in), _ptr(dW), _ptr(db), V, flags, io, form_code(form), ws.ptr(),
-                               ws.nbytes, prec, _stream(a_in)))
+                               _ptr(da_in), _ptr(dW), _ptr(db), V, flags, io, _ptr(relu_bits), form_code(form),
+                               ws.ptr(), ws.nbytes, prec, _stream(a_in)))
     return da_in, (dW if need_weight_grad else None), db
 
 

@@ -46,9 +46,9 @@ SIGNATURES = {
     "dlm_lsc_workspace_bytes": (_st, [_p, _int, _int, _i64, _int, _int, C.POINTER(C.c_size_t)]),
     "dlm_lsc_fwd": (_st, [_p, _p, _int, _p, _p, _int, _p, _i64, _int, _int, _p, C.c_size_t, _int, _p]),
     "dlm_lsc_bwd": (_st, [_p, _p, _int, _p, _int, _p, _p, _p, _p, _p, _i64, _int, _int, _p, C.c_size_t, _int, _p]),
-    "dlm_lsc_fwd_io": (_st, [_p, _p, _int, _p, _p, _int, _p, _i64, _int, _int, _int, _p, C.c_size_t, _int, _p]),
-    "dlm_lsc_bwd_io": (_st, [_p, _p, _int, _p, _int, _p, _p, _p, _p, _p, _i64, _int, _int, _int, _p, C.c_size_t, _int,
-                             _p]),
+    "dlm_lsc_fwd_io": (_st, [_p, _p, _int, _p, _p, _int, _p, _i64, _int, _int, _p, _int, _p, C.c_size_t, _int, _p]),
+    "dlm_lsc_bwd_io": (_st, [_p, _p, _int, _p, _int, _p, _p, _p, _p, _p, _i64, _int, _int, _p, _int, _p, C.c_size_t,
+                             _int, _p]),
     "dlm_mse_workspace_bytes": (C.c_size_t, [_i64]),
     "dlm_mse_fwd_bwd": (_st, [_p, _p, _i64, _p, _p, _p, C.c_size_t, _p]),
     "dlm_adam_step": (_st, [_p, _p, _p, _p, _i64, C.c_float, C.c_float, C.c_float, C.c_float, _i64, _p]),

@@ -890,8 +890,8 @@ dlm_status fold_weights(const dlm_lsc_plan *p, int C, int O, const float *W, con
 }
 
 dlm_status lsc_fwd_folded(const dlm_lsc_plan *p, const void *a_in, int C, const float *W, const float *bias, int O,
-                          void *a_out, int64_t V, int fuse_relu, int io, void *ws, size_t ws_bytes, dlm_precision prec,
-                          void *stream) {
+                          void *a_out, int64_t V, int fuse_relu, int io, uint16_t *relu_bits, void *ws, size_t ws_bytes,
+                          dlm_precision prec, void *stream) {
   if (ws_bytes < fold_ws_need(p, C, O))
     return fail(DLM_EWORKSPACE, "workspace of %zu bytes is below the %zu-byte minimum", ws_bytes, fold_ws_need(p, C, O));
   FoldWs w = fold_ws_carve(p, C, O, ws);
@@ -914,15 +914,17 @@ dlm_status lsc_fwd_folded(const dlm_lsc_plan *p, const void *a_in, int C, const 
   t.K = CK;
   t.relu = fuse_relu ? 1 : 0;
   t.op = kOpFoldFwd;
+  t.relu_bits_out = fuse_relu ? relu_bits : nullptr;
   TimedScope ts("lsc_folded_fwd", stream,
-                double(V) * (CK * ((io & DLM_IO_IN_BF16) ? 2.0 : 4.0) + double(M) * ((io & DLM_IO_OUT_BF16) ? 2.0 : 4.0)),
+                double(V) * (CK * ((io & DLM_IO_IN_BF16) ? 2.0 : 4.0) + double(M) * ((io & DLM_IO_OUT_BF16) ? 2.0 : 4.0) +
+                             (t.relu_bits_out ? M / 8.0 : 0.0)),
                 2.0 * double(V) * M * CK);
   return launched(launch_table_gemm(t, prec, stream));
 }
 
 dlm_status lsc_bwd_folded(const dlm_lsc_plan *p, const void *a_in, int C, const float *W, int O, const void *a_out,
                           const void *da_out, void *da_in, float *dW, float *dbias, int64_t V, int relu_flags, int io,
-                          void *ws, size_t ws_bytes, dlm_precision prec, void *stream) {
+                          const uint16_t *relu_bits, void *ws, size_t ws_bytes, dlm_precision prec, void *stream) {
   if (ws_bytes < fold_ws_need(p, C, O))
     return fail(DLM_EWORKSPACE, "workspace of %zu bytes is below the %zu-byte minimum", ws_bytes, fold_ws_need(p, C, O));
   FoldWs w = fold_ws_carve(p, C, O, ws);
@@ -942,13 +944,15 @@ dlm_status lsc_bwd_folded(const dlm_lsc_plan *p, const void *a_in, int C, const 
     t.Bf = w.TwT;
     t.Bh = w.TwTh;
     t.ldb_f = t.ldb_h = int64_t(pad32(size_t(M)));
+    const bool bits = (relu_flags & DLM_RELU_IN) && relu_bits;  // mask from the forward's ReLU bits
     if (in_h) {
       t.Ch = static_cast<uint16_t *>(da_in);
-      t.out_mask_h = (relu_flags & DLM_RELU_IN) ? static_cast<const uint16_t *>(a_in) : nullptr;
+      t.out_mask_h = (relu_flags & DLM_RELU_IN) && !bits ? static_cast<const uint16_t *>(a_in) : nullptr;
     } else {
       t.C = static_cast<float *>(da_in);
-      t.out_mask = (relu_flags & DLM_RELU_IN) ? static_cast<const float *>(a_in) : nullptr;
+      t.out_mask = (relu_flags & DLM_RELU_IN) && !bits ? static_cast<const float *>(a_in) : nullptr;
     }
+    t.relu_bits_in = bits ? relu_bits : nullptr;
     t.ldc = CK;
     t.M = V;
     t.N = CK;
@@ -957,7 +961,8 @@ dlm_status lsc_bwd_folded(const dlm_lsc_plan *p, const void *a_in, int C, const 
     const double ob = out_h ? 2.0 : 4.0, ib = in_h ? 2.0 : 4.0;  // bytes per element
     const bool omask = t.out_mask || t.out_mask_h;
     TimedScope ts("lsc_folded_bwd_data", stream,
-                  double(V) * (double(M) * (mask ? 2.0 : 1.0) * ob + CK * (omask ? 2.0 : 1.0) * ib),
+                  double(V) * (double(M) * (mask ? 2.0 : 1.0) * ob + CK * (omask ? 2.0 : 1.0) * ib +
+                               (t.relu_bits_in ? CK / 8.0 : 0.0)),
                   2.0 * double(V) * M * CK);
     if ((s = launched(launch_table_gemm(t, prec, stream))) != DLM_OK) return s;
   }
@@ -1019,25 +1024,30 @@ dlm_status io_check(const dlm_lsc_plan *p, int C, int O, int io, dlm_lsc_form fo
 }  // namespace
 
 dlm_status dlm_lsc_fwd_io(const dlm_lsc_plan *p, const void *a_in, int C, const float *W, const float *bias, int O,
-                          void *a_out, int64_t V, int fuse_relu, int io_flags, dlm_lsc_form form, void *ws,
-                          size_t ws_bytes, dlm_precision prec, void *stream) {
-  if (io_flags == 0)
+                          void *a_out, int64_t V, int fuse_relu, int io_flags, uint16_t *relu_bits, dlm_lsc_form form,
+                          void *ws, size_t ws_bytes, dlm_precision prec, void *stream) {
+  if (io_flags == 0 && !relu_bits)
     return dlm_lsc_fwd(p, static_cast<const float *>(a_in), C, W, bias, O, static_cast<float *>(a_out), V, fuse_relu,
                        form, ws, ws_bytes, prec, stream);
   dlm_status s = lsc_check(p, C, O, V, prec);
   if (s != DLM_OK) return s;
   if ((s = io_check(p, C, O, io_flags, form, prec, a_in, nullptr, a_out, nullptr)) != DLM_OK) return s;
+  if (relu_bits && (form != DLM_LSC_FOLDED || !fuse_relu || (O * p->K_out) % 16 != 0))
+    return fail(DLM_EINVAL, "ReLU bits need the folded form, fuse_relu and O*K_out (%d) a multiple of 16",
+                O * p->K_out);
   if (V == 0) return ok();
   if (!a_in || !W || !a_out || !ws) return fail(DLM_EINVAL, "null device pointer");
-  s = lsc_fwd_folded(p, a_in, C, W, bias, O, a_out, V, fuse_relu, io_flags, ws, ws_bytes, prec, stream);
+  s = lsc_fwd_folded(p, a_in, C, W, bias, O, a_out, V, fuse_relu, io_flags, relu_bits, ws, ws_bytes, prec, stream);
   return s == DLM_OK ? ok() : s;
 }
 
 dlm_status dlm_lsc_bwd_io(const dlm_lsc_plan *p, const void *a_in, int C, const float *W, int O, const void *a_out,
                           const void *da_out, void *da_in, float *dW, float *dbias, int64_t V, int relu_flags,
-                          int io_flags, dlm_lsc_form form, void *ws, size_t ws_bytes, dlm_precision prec,
-                          void *stream) {
-  if (io_flags == 0)
+                          int io_flags, const uint16_t *relu_bits, dlm_lsc_form form, void *ws, size_t ws_bytes,
+                          dlm_precision prec, void *stream) {
+  if (relu_bits && (form != DLM_LSC_FOLDED || !(relu_flags & DLM_RELU_IN) || (C * p->K_in) % 16 != 0))
+    return fail(DLM_EINVAL, "ReLU bits need the folded form, DLM_RELU_IN and C*K_in a multiple of 16");
+  if (io_flags == 0 && !relu_bits)
     return dlm_lsc_bwd(p, static_cast<const float *>(a_in), C, W, O, static_cast<const float *>(a_out),
                        static_cast<const float *>(da_out), static_cast<float *>(da_in), dW, dbias, V, relu_flags, form,
                        ws, ws_bytes, prec, stream);
@@ -1046,12 +1056,14 @@ dlm_status dlm_lsc_bwd_io(const dlm_lsc_plan *p, const void *a_in, int C, const 
   if ((s = io_check(p, C, O, io_flags, form, prec, a_in, da_in, a_out, da_out)) != DLM_OK) return s;
   if (!ws) return fail(DLM_EINVAL, "workspace is NULL");
   if (relu_flags & ~(DLM_RELU_OUT | DLM_RELU_IN)) return fail(DLM_EINVAL, "unknown relu flags 0x%x", relu_flags);
-  if (relu_flags & DLM_RELU_OUT)
+  if ((relu_flags & DLM_RELU_OUT) && io_flags)
     return fail(DLM_EINVAL, "DLM_RELU_OUT with bfloat16 activations: mask in the next layer (DLM_RELU_IN) instead");
+  if ((relu_flags & DLM_RELU_OUT) && relu_bits)
+    return fail(DLM_EINVAL, "DLM_RELU_OUT with ReLU bits: mask in the next layer (DLM_RELU_IN) instead");
   if (dbias && !dW) return fail(DLM_EINVAL, "dbias without dW is not supported");
   if (V > 0 && (!a_in || !W || !da_out)) return fail(DLM_EINVAL, "null device pointer");
-  s = lsc_bwd_folded(p, a_in, C, W, O, a_out, da_out, da_in, dW, dbias, V, relu_flags, io_flags, ws, ws_bytes, prec,
-                     stream);
+  s = lsc_bwd_folded(p, a_in, C, W, O, a_out, da_out, da_in, dW, dbias, V, relu_flags, io_flags, relu_bits, ws,
+                     ws_bytes, prec, stream);
   return s == DLM_OK ? ok() : s;
 }
 
@@ -1064,7 +1076,7 @@ dlm_status dlm_lsc_fwd(const dlm_lsc_plan *p, const float *a_in, int C, const fl
   if (V == 0) return ok();
   if (!a_in || !W || !a_out || !ws) return fail(DLM_EINVAL, "null device pointer");
   if (form == DLM_LSC_FOLDED) {
-    s = lsc_fwd_folded(p, a_in, C, W, bias, O, a_out, V, fuse_relu, 0, ws, ws_bytes, prec, stream);
+    s = lsc_fwd_folded(p, a_in, C, W, bias, O, a_out, V, fuse_relu, 0, nullptr, ws, ws_bytes, prec, stream);
     return s == DLM_OK ? ok() : s;
   }
   const int64_t Vc = lsc_chunk(p, C, O, V, ws_bytes);
@@ -1134,8 +1146,8 @@ dlm_status dlm_lsc_bwd(const dlm_lsc_plan *p, const float *a_in, int C, const fl
   if (V > 0 && (!a_in || !W || !da_out)) return fail(DLM_EINVAL, "null device pointer");
   if (form == DLM_LSC_FOLDED) {
     if (V > 0 && !W) return fail(DLM_EINVAL, "null device pointer");
-    s = lsc_bwd_folded(p, a_in, C, W, O, a_out, da_out, da_in, dW, dbias, V, relu_flags, 0, ws, ws_bytes, prec,
-                       stream);
+    s = lsc_bwd_folded(p, a_in, C, W, O, a_out, da_out, da_in, dW, dbias, V, relu_flags, 0, nullptr, ws, ws_bytes,
+                       prec, stream);
     return s == DLM_OK ? ok() : s;
   }
   const int T = p->T, m = int(p->m);

@@ -83,6 +83,11 @@ struct TableGemm {
   const uint16_t *Ah = nullptr;
   uint16_t *Ch = nullptr;
   const uint16_t *out_mask_h = nullptr;
+  // ReLU bit masks (streaming core; N a multiple of 16): the forward writes
+  // bit (output > 0) of every output, one uint16 per 16 columns
+  // ([M][N / 16]); the input gradient masks by them instead of out_mask
+  uint16_t *relu_bits_out = nullptr;
+  const uint16_t *relu_bits_in = nullptr;
 };
 int launch_table_gemm(const TableGemm &g, dlm_precision prec, void *stream);
 

@@ -501,7 +501,8 @@ static int table_gemm_op(const TableGemm &t, dlm_precision prec, hipStream_t st)
 
 int launch_table_gemm(const TableGemm &t, dlm_precision prec, void *stream) {
   if (stream_table_ok(t, prec)) return launch_stream_table(t, prec, stream);
-  if (t.Ah || t.Ch || t.out_mask_h) return -3;  // bfloat16 activations: streaming core only
+  if (t.Ah || t.Ch || t.out_mask_h || t.relu_bits_out || t.relu_bits_in)
+    return -3;  // bfloat16 activations and ReLU bits: streaming core only
   hipStream_t st = (hipStream_t)stream;
   switch (t.op) {
     case kOpS2shFwd: return table_gemm_op<kOpS2shFwd>(t, prec, st);

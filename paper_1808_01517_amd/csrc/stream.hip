@@ -683,18 +683,44 @@ bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 
 
 // Row-major output with compile-time side inputs: BIAS adds bias_n[n], MASK
 // zeroes entries where omask (indexed as C) <= 0; optional ReLU in between.
-template <bool BIAS, bool MASK>
+// ReLU bit masks (BM): 1 = write bit (stored value > 0) of every output to
+// obits, 2 = take the mask (MASK) from mbits instead of omask.  Bit c % 16 of
+// word r * ldm + c / 16 belongs to element (r, c); N is a multiple of 16, so
+// a 16-column tile is one word, held four bits per lane by the four lanes
+// (q16, g4) of one row.
+__device__ __forceinline__ floatx4 bits_mask(const uint16_t *mbits, int64_t ldm, int64_t r, int n) {
+  const unsigned w = (unsigned)mbits[r * ldm + n / 16] >> (n & 15);
+  return floatx4{(float)(w & 1u), (float)((w >> 1) & 1u), (float)((w >> 2) & 1u), (float)((w >> 3) & 1u)};
+}
+__device__ __forceinline__ void bits_store(uint16_t *obits, int64_t ldm, int64_t r, int n, unsigned nib) {
+  // OR the nibbles of the four lanes of this row (lanes q16 + 16 g4)
+  unsigned w = nib << (n & 15);
+  w |= __shfl_xor(w, 16);
+  w |= __shfl_xor(w, 32);
+  if ((n & 15) == 0) obits[r * ldm + n / 16] = (uint16_t)w;
+}
+
+// Row-major output with compile-time side inputs: BIAS adds bias_n[n], MASK
+// zeroes entries where omask (indexed as C) <= 0, or where the ReLU bit is
+// clear (BM = 2); optional ReLU in between; BM = 1 also writes the ReLU bits.
+template <bool BIAS, bool MASK, int BM = 0>
 struct CRowSide {
   static constexpr bool kSide = BIAS || MASK;
   float *C;
   int64_t ldc;
   int relu;
   const float *bias_n, *omask;
+  const uint16_t *mbits = nullptr;
+  uint16_t *obits = nullptr;
+  int64_t ldm = 0;
   __device__ void operator()(int64_t r, int n, int, float v) const {
     const int64_t o = r * ldc + n;
     if constexpr (BIAS) v += bias_n[n];
     if (relu) v = fmaxf(v, 0.0f);
-    if constexpr (MASK) v = omask[o] > 0.0f ? v : 0.0f;
+    if constexpr (MASK) {
+      if constexpr (BM == 2) v = (mbits[r * ldm + n / 16] >> (n & 15)) & 1u ? v : 0.0f;
+      else v = omask[o] > 0.0f ? v : 0.0f;
+    }
     C[o] = v;
   }
   __device__ void store4(int64_t r, int n, int g, floatx4 v) const {
@@ -705,22 +731,27 @@ struct CRowSide {
     else return floatx4{0.f, 0.f, 0.f, 0.f};
   }
   __device__ floatx4 elside(int64_t r, int n, int) const {
-    if constexpr (MASK) return ld4(omask + r * ldc + n);
+    if constexpr (MASK && BM == 2) return bits_mask(mbits, ldm, r, n);
+    else if constexpr (MASK) return ld4(omask + r * ldc + n);
     else return floatx4{1.f, 1.f, 1.f, 1.f};
   }
   __device__ void store4s(int64_t r, int n, int, floatx4 v, floatx4 cb, floatx4 em) const {
+    unsigned nib = 0;
     for (int q = 0; q < 4; ++q) {
       if constexpr (BIAS) v[q] += cb[q];
       if (relu) v[q] = fmaxf(v[q], 0.0f);
       if constexpr (MASK) v[q] = em[q] > 0.0f ? v[q] : 0.0f;
+      nib |= (v[q] > 0.0f ? 1u : 0u) << q;
     }
     __builtin_memcpy(C + r * ldc + n, &v, 16);
+    if constexpr (BM == 1) bits_store(obits, ldm, r, n, nib);
   }
 };
 
 // The same with a bfloat16 output (RNE) and a bfloat16 mask: activations and
 // their gradients stored in bfloat16.  ldc a multiple of 4, 8-byte aligned rows.
-template <bool BIAS, bool MASK>
+// ReLU bits (BM = 1) describe the stored (rounded) values.
+template <bool BIAS, bool MASK, int BM = 0>
 struct CRowSideH {
   static constexpr bool kSide = BIAS || MASK;
   uint16_t *C;
@@ -728,12 +759,18 @@ struct CRowSideH {
   int relu;
   const float *bias_n;
   const uint16_t *omask;
+  const uint16_t *mbits = nullptr;
+  uint16_t *obits = nullptr;
+  int64_t ldm = 0;
   __device__ static float widen(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
   __device__ void operator()(int64_t r, int n, int, float v) const {
     const int64_t o = r * ldc + n;
     if constexpr (BIAS) v += bias_n[n];
     if (relu) v = fmaxf(v, 0.0f);
-    if constexpr (MASK) v = widen(omask[o]) > 0.0f ? v : 0.0f;
+    if constexpr (MASK) {
+      if constexpr (BM == 2) v = (mbits[r * ldm + n / 16] >> (n & 15)) & 1u ? v : 0.0f;
+      else v = widen(omask[o]) > 0.0f ? v : 0.0f;
+    }
     C[o] = to_bf16_bits(v);
   }
   __device__ void store4(int64_t r, int n, int g, floatx4 v) const {
@@ -744,7 +781,9 @@ struct CRowSideH {
     else return floatx4{0.f, 0.f, 0.f, 0.f};
   }
   __device__ floatx4 elside(int64_t r, int n, int) const {
-    if constexpr (MASK) {
+    if constexpr (MASK && BM == 2) {
+      return bits_mask(mbits, ldm, r, n);
+    } else if constexpr (MASK) {
       uint16_t h[4];
       __builtin_memcpy(h, omask + r * ldc + n, 8);
       return floatx4{widen(h[0]), widen(h[1]), widen(h[2]), widen(h[3])};
@@ -754,13 +793,16 @@ struct CRowSideH {
   }
   __device__ void store4s(int64_t r, int n, int, floatx4 v, floatx4 cb, floatx4 em) const {
     uint16_t h[4];
+    unsigned nib = 0;
     for (int q = 0; q < 4; ++q) {
       if constexpr (BIAS) v[q] += cb[q];
       if (relu) v[q] = fmaxf(v[q], 0.0f);
       if constexpr (MASK) v[q] = em[q] > 0.0f ? v[q] : 0.0f;
       h[q] = to_bf16_bits(v[q]);
+      nib |= (widen(h[q]) > 0.0f ? 1u : 0u) << q;
     }
     __builtin_memcpy(C + r * ldc + n, h, 8);
+    if constexpr (BM == 1) bits_store(obits, ldm, r, n, nib);
   }
 };
 
@@ -788,11 +830,20 @@ int stream_table_c(AO ao, BO bo, CS cs, const TableGemm &t, hipStream_t st) {
 // the forward GEMM adds the folded bias; the input-gradient GEMM may mask
 template <int OP, bool F32, class AO, class BO>
 int stream_table(AO ao, BO bo, const TableGemm &t, hipStream_t st) {
+  const int64_t ldm = t.N / 16;  // ReLU-bit words per row
   if constexpr (!F32) {
     if (t.Ch) {  // bfloat16 output (and mask)
       if constexpr (OP == kOpFoldFwd) {
+        if (t.relu_bits_out)
+          return stream_table_c<OP, F32>(
+              ao, bo, CRowSideH<true, false, 1>{t.Ch, t.ldc, t.relu, t.bias_n, nullptr, nullptr, t.relu_bits_out, ldm},
+              t, st);
         return stream_table_c<OP, F32>(ao, bo, CRowSideH<true, false>{t.Ch, t.ldc, t.relu, t.bias_n, nullptr}, t, st);
       } else {
+        if (t.relu_bits_in)
+          return stream_table_c<OP, F32>(
+              ao, bo, CRowSideH<false, true, 2>{t.Ch, t.ldc, t.relu, nullptr, nullptr, t.relu_bits_in, nullptr, ldm},
+              t, st);
         if (t.out_mask_h)
           return stream_table_c<OP, F32>(ao, bo, CRowSideH<false, true>{t.Ch, t.ldc, t.relu, nullptr, t.out_mask_h},
                                          t, st);
@@ -801,8 +852,15 @@ int stream_table(AO ao, BO bo, const TableGemm &t, hipStream_t st) {
     }
   }
   if constexpr (OP == kOpFoldFwd) {
+    if (t.relu_bits_out)
+      return stream_table_c<OP, F32>(
+          ao, bo, CRowSide<true, false, 1>{t.C, t.ldc, t.relu, t.bias_n, nullptr, nullptr, t.relu_bits_out, ldm}, t,
+          st);
     return stream_table_c<OP, F32>(ao, bo, CRowSide<true, false>{t.C, t.ldc, t.relu, t.bias_n, nullptr}, t, st);
   } else {
+    if (t.relu_bits_in)
+      return stream_table_c<OP, F32>(
+          ao, bo, CRowSide<false, true, 2>{t.C, t.ldc, t.relu, nullptr, nullptr, t.relu_bits_in, nullptr, ldm}, t, st);
     if (t.out_mask)
       return stream_table_c<OP, F32>(ao, bo, CRowSide<false, true>{t.C, t.ldc, t.relu, nullptr, t.out_mask}, t, st);
     return stream_table_c<OP, F32>(ao, bo, CRowSide<false, false>{t.C, t.ldc, t.relu, nullptr, nullptr}, t, st);
@@ -839,6 +897,11 @@ constexpr int64_t kMaxStreamLd = int64_t(1) << 22;
 
 bool stream_table_ok(const TableGemm &t, dlm_precision prec) {
   if (t.groups != 1 || t.mask != nullptr || (t.op != kOpFoldFwd && t.op != kOpFoldBwdData)) return false;
+  if (t.relu_bits_out || t.relu_bits_in) {  // ReLU bits: one word per 16 columns
+    if (t.N % 16 != 0) return false;
+    if (t.relu_bits_out && (t.op != kOpFoldFwd || !t.relu)) return false;
+    if (t.relu_bits_in && (t.op != kOpFoldBwdData || t.out_mask || t.out_mask_h)) return false;
+  }
   if (t.Ah || t.Ch || t.out_mask_h) {  // bfloat16 activations: BF16 only, 16-byte rows
     if (prec != DLM_BF16) return false;
     if (t.Ah && (t.A || t.lda % 8 != 0 || t.K % 8 != 0 || !aligned16(t.Ah))) return false;
