@@ -693,10 +693,13 @@ __device__ __forceinline__ floatx4 bits_mask(const uint16_t *mbits, int64_t ldm,
   return floatx4{(float)(w & 1u), (float)((w >> 1) & 1u), (float)((w >> 2) & 1u), (float)((w >> 3) & 1u)};
 }
 __device__ __forceinline__ void bits_store(uint16_t *obits, int64_t ldm, int64_t r, int n, unsigned nib) {
-  // OR the nibbles of the four lanes of this row (lanes q16 + 16 g4)
+  // OR the nibbles of the four lanes of this row (lanes q16 + 16 g4): the
+  // row swaps exchange lane l with l ^ 16, then with l ^ 32, in registers
   unsigned w = nib << (n & 15);
-  w |= __shfl_xor(w, 16);
-  w |= __shfl_xor(w, 32);
+  const auto s16 = __builtin_amdgcn_permlane16_swap(w, w, false, false);
+  w = s16[0] | s16[1];
+  const auto s32 = __builtin_amdgcn_permlane32_swap(w, w, false, false);
+  w = s32[0] | s32[1];
   if ((n & 15) == 0) obits[r * ldm + n / 16] = (uint16_t)w;
 }
 
