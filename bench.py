@@ -54,8 +54,9 @@ def parse():
                     help="run the loss head as SH2Signal, MSE and SH2Signal adjoint in three calls")
     ap.add_argument("--relu-mask", choices=["auto", "bits", "activation"], default="auto",
                     help="source of the hidden ReLU's backward mask: one bit per element written by the forward, or "
-                         "the stored activation (auto: bits in BF16, where the step is memory-bound; the activation "
-                         "in FP32, where the extra epilogue work costs more than the saved reads)")
+                         "the stored activation (auto: bits for the 1M-voxel BF16 step, which is memory-bound; the "
+                         "activation in FP32, where the extra epilogue work costs more than the saved reads, and for "
+                         "the 8192-voxel four-layer step, whose activations stay in cache)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--with-copy-calibration", action="store_true",
@@ -186,7 +187,8 @@ def bench_c4(args):
     w = dg.C4
     B = w.voxels
     half = prec == "bf16" and form == "folded" and not args.fp32_activations
-    net, acq = apps.c4_network(prec, form, recompute=(0, 2), batch=B, bf16_activations=half)
+    bits = args.relu_mask == "bits"  # auto: the activation mask at 8 192-voxel batches
+    net, acq = apps.c4_network(prec, form, recompute=(0, 2), batch=B, bf16_activations=half, relu_bits=bits)
     nb = 8
     batches = []
     for i in range(nb):
@@ -215,7 +217,8 @@ def bench_c4(args):
               "vs_baseline": None, "dtype": "f32" if prec == "fp32" else "bf16", "data": "synthetic",
               "config": {"workload": w.name, "batch": B, "lsc_channels": list(w.channels), "sh_order": w.sh_order,
                          "distortion_deg": 3.0, "recompute_layers": [1, 3], "lsc_form": form, "precision": prec,
-                         "hidden_activation_storage": "bf16" if half else "f32"}}
+                         "hidden_activation_storage": "bf16" if half else "f32",
+                         "relu_backward_mask": "bits" if net.relu_bits else "activation"}}
     if not args.no_kernel_timing:
         import paper_1808_01517_amd as dl
         dl.timing_reset()

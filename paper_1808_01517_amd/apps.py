@@ -66,7 +66,7 @@ def nrmse(pred: torch.Tensor, ref: torch.Tensor) -> float:
 # --------------------------------------------------- differentiation workload
 
 def c4_network(precision="fp32", form="folded", recompute=(0, 2), device="cuda:0", weights=None, batch=8192,
-               bf16_activations=False):
+               bf16_activations=False, relu_bits=False):
     w = dg.C4
     acq = dg.make_acquisition(w.config, w.shell_b, w.dirs_per_shell, w.perturb_deg, w.n_b0)
     plan = SHPlan(acq.bvecs, acq.bvals, w.sh_order, w.lb_lambda)
@@ -77,7 +77,7 @@ def c4_network(precision="fp32", form="folded", recompute=(0, 2), device="cuda:0
         weights = [dg.lsc_weights(w.config, k, ch[k], ch[k + 1], 1 + sum(w.kernel_sizes)) for k in range(len(ch) - 1)]
     net = LSCNetwork(plan, plan, dg.lsc_sampled_gradients(w), specs, w.kernel_sizes, w.angular_distance,
                      w.lb_lambda, weights=weights, precision=precision, form=form, recompute=recompute,
-                     device=device, max_batch=batch, bf16_activations=bf16_activations)
+                     device=device, max_batch=batch, bf16_activations=bf16_activations, relu_bits=relu_bits)
     return net, acq
 
 
@@ -93,7 +93,7 @@ def c4_batch(acq, index: int, V: int = 8192):
 # ------------------------------------------------------------ learned form
 
 def learned_setup(train_voxels=None, eval_voxels=262144, precision="bf16", form="folded", device="cuda:0",
-                  batch=8192, subset=15, bf16_activations=False):
+                  batch=8192, subset=15, bf16_activations=False, relu_bits=False):
     w = dg.C5
     acq = dg.make_acquisition(w.config, w.shell_b, w.dirs_per_shell, w.perturb_deg, w.n_b0)
     idx = [dg.farthest_point_subset(d, subset) for d in acq.shell_dirs]
@@ -111,7 +111,7 @@ def learned_setup(train_voxels=None, eval_voxels=262144, precision="bf16", form=
     weights = [dg.lsc_weights(w.config, k, ch[k], ch[k + 1], 1 + sum(w.kernel_sizes)) for k in range(len(ch) - 1)]
     net = LSCNetwork(plan_in, plan_out, dg.lsc_sampled_gradients(w), specs, w.kernel_sizes, w.angular_distance,
                      w.lb_lambda, weights=weights, precision=precision, form=form, device=device, max_batch=batch,
-                     bf16_activations=bf16_activations)
+                     bf16_activations=bf16_activations, relu_bits=relu_bits)
     # the plain method: order-4 fit from the same subset, evaluated on the full table
     fit_in = SHPlan(sub.bvecs, sub.bvals, w.sh_order_lsc_in, w.lb_lambda)
     fit_in0 = SHPlan(sub.bvecs, sub.bvals, w.sh_order_lsc_in, 0.0)
@@ -134,10 +134,11 @@ def predict(setup, x_sub: torch.Tensor, batch=65536) -> torch.Tensor:
 
 
 def run_learned(train_voxels=1 << 22, eval_voxels=262144, epochs=8, lr=2e-3, batch=8192, precision="bf16",
-                form="folded", device="cuda:0", log=sys.stderr, bf16_activations=True):
+                form="folded", device="cuda:0", log=sys.stderr, bf16_activations=True, relu_bits=False):
     dev = torch.device(device)
     t0 = time.perf_counter()
-    S = learned_setup(train_voxels, eval_voxels, precision, form, device, batch, bf16_activations=bf16_activations)
+    S = learned_setup(train_voxels, eval_voxels, precision, form, device, batch, bf16_activations=bf16_activations,
+                      relu_bits=relu_bits)
     w, acq, cols, net = S["w"], S["acq"], S["cols"], S["net"]
     xtr, ctr = _gen(acq, train_voxels, w, dg.STREAM_DATA)
     xev, cev = _gen(acq, eval_voxels, w, dg.STREAM_HELDOUT)
@@ -176,7 +177,7 @@ def run_learned(train_voxels=1 << 22, eval_voxels=262144, epochs=8, lr=2e-3, bat
     res = {
         "workload": w.name, "train_voxels": train_voxels, "eval_voxels": eval_voxels, "epochs": epochs,
         "batch": batch, "optimizer": f"Adam lr {lr} halved every {max(1, epochs // 3)} epochs", "precision": precision,
-        "lsc_form": form,
+        "lsc_form": form, "relu_backward_mask": "bits" if net.relu_bits else "activation",
         "nrmse_net_vs_clean": nrmse(pred, y_ev), "nrmse_fit_vs_clean": nrmse(fit, y_ev),
         "nrmse_fit_lambda0_vs_clean": nrmse(fit0, y_ev),
         "nrmse_net_vs_noisy": nrmse(pred, x_ev_full), "nrmse_fit_vs_noisy": nrmse(fit, x_ev_full),
@@ -195,8 +196,10 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--precision", default="bf16")
     ap.add_argument("--form", default="folded")
+    ap.add_argument("--relu-mask", choices=["bits", "activation"], default="activation")
     a = ap.parse_args()
-    res, _, _ = run_learned(a.train_voxels, a.eval_voxels, a.epochs, a.lr, precision=a.precision, form=a.form)
+    res, _, _ = run_learned(a.train_voxels, a.eval_voxels, a.epochs, a.lr, precision=a.precision, form=a.form,
+                            relu_bits=a.relu_mask == "bits")
     print(json.dumps(res), flush=True)
 
 

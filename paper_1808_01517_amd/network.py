@@ -14,7 +14,10 @@ are bitwise identical to the run that keeps every activation.
 When the output table allows it, the loss step runs as one fused pass
 (SH2Signal, MSE and the SH2Signal adjoint).  With `bf16_activations` in the
 BF16 folded form, hidden activations and their gradients are stored in
-bfloat16, which leaves every value the contractions see unchanged.
+bfloat16, which leaves every value the contractions see unchanged.  With
+`relu_bits` each hidden ReLU's backward mask is read from
+one bit per element that the forward writes beside the activation; the
+results are bitwise those of the activation mask.
 """
 from __future__ import annotations
 
@@ -24,8 +27,8 @@ import numpy as np
 import torch
 
 from . import (DEFAULT_FORM, LSCPlan, SHPlan, Workspace, adam_step, lib, lsc_bwd, lsc_fwd, lsc_workspace_bytes,
-               mse_fwd_bwd, sh2signal_bwd, sh2signal_fwd, sh2signal_mse_fwd_bwd, sh2signal_mse_supported,
-               signal2sh_bwd, signal2sh_fwd)
+               mse_fwd_bwd, relu_bits_like, sh2signal_bwd, sh2signal_fwd, sh2signal_mse_fwd_bwd,
+               sh2signal_mse_supported, signal2sh_bwd, signal2sh_fwd)
 
 
 @dataclass
@@ -40,7 +43,7 @@ class LayerSpec:
 class LSCNetwork:
     def __init__(self, plan_in: SHPlan, plan_out: SHPlan, sampled_gradients, specs, kernel_sizes, angular_distance,
                  lb_lambda=0.006, weights=None, precision="fp32", form=DEFAULT_FORM, recompute=(), device="cuda:0",
-                 max_batch=8192, bf16_activations=False):
+                 max_batch=8192, bf16_activations=False, relu_bits=False):
         self.plan_in, self.plan_out = plan_in, plan_out
         self.specs = list(specs)
         self.precision, self.form = precision, form
@@ -48,6 +51,11 @@ class LSCNetwork:
         # folded form, rows of a multiple of 8 entries; the contractions round
         # them to bfloat16 on load anyway
         self.bf16_activations = bool(bf16_activations) and precision == "bf16" and form == "folded"
+        # a hidden ReLU's backward mask as one bit per element, written by the
+        # forward beside the activation (folded form); off by default: at
+        # batches of a few thousand voxels the activations stay in cache and
+        # the extra epilogue work outweighs the saved reads
+        self.relu_bits = bool(relu_bits) and form == "folded"
         self.recompute = set(int(k) for k in recompute)
         if any(k < 0 or k >= len(specs) - 1 for k in self.recompute):
             raise ValueError("only layers before the last can be recomputed")
@@ -95,6 +103,16 @@ class LSCNetwork:
             else:
                 self.acts.append(torch.empty(shape, dtype=dt, device=self.dev))
         self.grads = [torch.empty(a.shape, dtype=a.dtype, device=self.dev) for a in self.acts]
+        # bits[k] describes acts[k]; shared exactly as the activations are
+        self.bits = [None] * (n + 1)
+        shared_bits = {}
+        for k, (s, p) in enumerate(zip(self.specs, self.plans)):
+            if self.relu_bits and s.relu and k < n - 1 and (s.O * p.K_out) % 16 == 0:
+                a = self.acts[k + 1]
+                key = id(a)
+                if key not in shared_bits:
+                    shared_bits[key] = relu_bits_like(a)
+                self.bits[k + 1] = shared_bits[key]
         self.xhat = torch.empty((V, self.plan_out.n_dw), **f32)
         self.dxhat = torch.empty_like(self.xhat)
         self.loss = torch.empty((), **f32)
@@ -122,8 +140,10 @@ class LSCNetwork:
     # ------------------------------------------------------------ passes
     def _layer_fwd(self, k, V):
         s, p = self.specs[k], self.plans[k]
+        bits = self.bits[k + 1]
         lsc_fwd(p, self.acts[k][:V], self.W[k], self.b[k], relu=s.relu, out=self.acts[k + 1][:V],
-                precision=self.precision, workspace=self.ws, form=self.form)
+                precision=self.precision, workspace=self.ws, form=self.form,
+                relu_bits=None if bits is None else bits[:V])
 
     def _forward_sh(self, x: torch.Tensor) -> int:
         V = x.shape[0]
@@ -159,7 +179,8 @@ class LSCNetwork:
             lsc_bwd(p, self.acts[k][:V], self.W[k], self.grads[k + 1][:V],
                     a_out=self.acts[k + 1][:V] if relu_out else None, relu=relu_out, relu_in=relu_in,
                     need_input_grad=(k > 0 or need_input_grad), precision=self.precision, workspace=self.ws,
-                    outs=(self.grads[k][:V], self.dW[k], self.db[k]), form=self.form)
+                    outs=(self.grads[k][:V], self.dW[k], self.db[k]), form=self.form,
+                    relu_bits=self.bits[k][:V] if relu_in and self.bits[k] is not None else None)
         if need_input_grad:
             return signal2sh_bwd(self.plan_in, self.grads[0][:V], precision=self.precision)
         return None

@@ -135,6 +135,23 @@ def test_recompute_gives_identical_gradients():
         assert torch.equal(a.dW[k], b.dW[k]) and torch.equal(a.db[k], b.db[k])
 
 
+@pytest.mark.parametrize("prec,half", [("fp32", False), ("bf16", False), ("bf16", True)])
+def test_relu_bits_give_identical_gradients(prec, half):
+    """Hidden ReLU masks from the forward's bits (three hidden layers, two of
+    them recomputed into one shared buffer) against masks from the stored
+    activations: bitwise the same gradients and loss."""
+    a, acq = apps.c4_network(prec, "folded", recompute=(0, 2), batch=300, bf16_activations=half, relu_bits=True)
+    b, _ = apps.c4_network(prec, "folded", recompute=(0, 2), batch=300, bf16_activations=half, relu_bits=False)
+    assert sum(x is not None for x in a.bits) == 3 and all(x is None for x in b.bits)
+    _, x, clean = apps.c4_batch(acq, 2, V=300)
+    a.loss_and_grads(cu(x), cu(clean))
+    b.loss_and_grads(cu(x), cu(clean))
+    torch.cuda.synchronize()
+    assert torch.equal(a.loss, b.loss)
+    for k in range(4):
+        assert torch.equal(a.dW[k], b.dW[k]) and torch.equal(a.db[k], b.db[k])
+
+
 def test_checkpoint_resume_is_exact(tmp_path):
     def run(n_steps, net):
         for i in range(n_steps):
