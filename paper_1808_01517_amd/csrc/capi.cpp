@@ -39,6 +39,13 @@ dlm_status ok() {
   return DLM_OK;
 }
 
+dlm_status launched(int rc) {
+  if (rc == 0) return DLM_OK;
+  if (rc == -3)  // every launcher's code for an operand layout it does not take
+    return fail(DLM_EINVAL, "no kernel takes this operand layout (shape, row stride or alignment)");
+  return fail(DLM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
+}
+
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 bool have_device() {
@@ -508,7 +515,7 @@ dlm_status sh_apply(const dlm_sh_plan *p, const float *in, float *out, int64_t V
     } else {
       rc = launch_table_gemm(t, prec, stream);
     }
-    if (rc != 0) return fail(DLM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
+    if (rc != 0) return launched(rc);
   }
   return ok();
 }
@@ -842,11 +849,6 @@ dlm_status lsc_check(const dlm_lsc_plan *p, int C, int O, int64_t V, dlm_precisi
   if (V < 0) return fail(DLM_EINVAL, "V must be >= 0");
   if (prec != DLM_FP32 && prec != DLM_BF16) return fail(DLM_EINVAL, "unknown precision %d", int(prec));
   return DLM_OK;
-}
-
-dlm_status launched(int rc) {
-  if (rc == 0) return DLM_OK;
-  return fail(DLM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
 }
 
 }  // namespace
