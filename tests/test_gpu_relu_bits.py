@@ -106,6 +106,35 @@ def test_backward_with_relu_bits_matches_activation_mask(prec, store, O):
     assert all(v <= TOL[prec] for v in errs.values()), errs
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_relu_bits_on_short_rows(prec):
+    """Order 2 (6 coefficients), 3 -> 16 -> 3: rows of 96 entries (6 words),
+    the narrow-tile configuration of the streaming core in both directions."""
+    oplan, plan = _plan(L=2, ks=(6, 6), m=30)
+    V = 517
+    W1, b1 = _weights(26, 3, 16, plan.T)
+    W2, b2 = _weights(27, 16, 3, plan.T)
+    x = np.random.default_rng(8).standard_normal((V, 3, plan.K_in))
+    W1g, b1g, W2g = cuda(W1), cuda(b1), cuda(W2)
+    a1 = dl.lsc_fwd(plan, cuda(x), W1g, b1g, relu=True, precision=prec, form="folded")
+    bits = dl.relu_bits_like(a1)
+    assert tuple(bits.shape) == (V, 6)
+    bits.fill_(-1)
+    a1b = dl.lsc_fwd(plan, cuda(x), W1g, b1g, relu=True, precision=prec, form="folded", relu_bits=bits)
+    torch.cuda.synchronize()
+    assert torch.equal(a1b, a1)
+    assert np.array_equal(words(bits), pack_bits(a1))
+    da = cuda(np.random.default_rng(9).standard_normal((V, 3, plan.K_out)))
+    g_m, dW_m, db_m = dl.lsc_bwd(plan, a1, W2g, da, relu_in=True, precision=prec, form="folded")
+    g_b, dW_b, db_b = dl.lsc_bwd(plan, a1, W2g, da, relu_in=True, precision=prec, form="folded", relu_bits=bits)
+    torch.cuda.synchronize()
+    assert torch.equal(g_b, g_m) and torch.equal(dW_b, dW_m) and torch.equal(db_b, db_m)
+    a64 = a1.double().cpu().numpy()
+    _, z = olsc.lsc_forward(oplan, a64, W2, b2, False)
+    da_ref, _, _ = olsc.lsc_backward(oplan, a64, W2, z, da.double().cpu().numpy(), False)
+    assert rel(g_b, da_ref * (a64 > 0)) <= TOL[prec]
+
+
 def test_relu_bits_rejects_unsupported():
     oplan, plan = _plan()
     V = 16
