@@ -482,8 +482,7 @@ __device__ __forceinline__ void store_tiles(const CS &cs, const floatx4 (&acc)[C
         if (i >= CF::TM) break;
         const int64_t r = m0 + (wm * CF::TM + i) * 16 + q16;
         if (r >= M) continue;
-#pragma unroll
-        for (int j = 0; j < CF::TN; ++j) {
+        auto one = [&](int j) {
           const int n = n0 + (wn * CF::TN + j) * 16 + 4 * g4;
           if (n + 3 < N) {
             cs.store4s(r, n, z, acc[i][j], cb[j], em[ii][j]);
@@ -491,6 +490,25 @@ __device__ __forceinline__ void store_tiles(const CS &cs, const floatx4 (&acc)[C
             for (int q = 0; q < 4; ++q)
               if (n + q < N) cs(r, n + q, z, acc[i][j][q]);
           }
+        };
+        if constexpr (CS::kPair) {
+          // two adjacent tiles per 16-byte store when both lie inside N
+          // (a condition uniform over the wave, so every lane swaps)
+#pragma unroll
+          for (int jp = 0; jp < CF::TN / 2; ++jp) {
+            const int j = 2 * jp;
+            const int nt = n0 + (wn * CF::TN + j) * 16;
+            if (nt + 32 <= N) {
+              cs.store_pair(r, nt, g4, acc[i][j], cb[j], em[ii][j], acc[i][j + 1], cb[j + 1], em[ii][j + 1]);
+            } else {
+              one(j);
+              one(j + 1);
+            }
+          }
+          if constexpr (CF::TN % 2 != 0) one(CF::TN - 1);
+        } else {
+#pragma unroll
+          for (int j = 0; j < CF::TN; ++j) one(j);
         }
       }
     }
@@ -709,6 +727,7 @@ __device__ __forceinline__ void bits_store(uint16_t *obits, int64_t ldm, int64_t
 template <bool BIAS, bool MASK, int BM = 0>
 struct CRowSide {
   static constexpr bool kSide = BIAS || MASK;
+  static constexpr bool kPair = false;
   float *C;
   int64_t ldc;
   int relu;
@@ -757,6 +776,7 @@ struct CRowSide {
 template <bool BIAS, bool MASK, int BM = 0>
 struct CRowSideH {
   static constexpr bool kSide = BIAS || MASK;
+  static constexpr bool kPair = true;
   uint16_t *C;
   int64_t ldc;
   int relu;
@@ -806,6 +826,61 @@ struct CRowSideH {
     }
     __builtin_memcpy(C + r * ldc + n, h, 8);
     if constexpr (BM == 1) bits_store(obits, ldm, r, n, nib);
+  }
+  // Tiles j (columns nt..nt+15) and j+1 (nt+16..nt+31) of one row: lane g4
+  // holds columns 4 g4..4 g4+3 of both.  A row swap (lane l with l ^ 16,
+  // i.e. g4 with g4 ^ 1) hands each even lane its neighbour's half of tile
+  // j and each odd lane its neighbour's half of tile j+1, so every lane
+  // stores 8 contiguous columns (16 bytes) with one instruction.
+  __device__ void store_pair(int64_t r, int nt, int g4, floatx4 v0, floatx4 cb0, floatx4 em0, floatx4 v1,
+                             floatx4 cb1, floatx4 em1) const {
+    uint32_t w0[2], w1[2];
+    unsigned nib0 = 0, nib1 = 0;
+    for (int q = 0; q < 4; ++q) {
+      if constexpr (BIAS) {
+        v0[q] += cb0[q];
+        v1[q] += cb1[q];
+      }
+      if (relu) {
+        v0[q] = fmaxf(v0[q], 0.0f);
+        v1[q] = fmaxf(v1[q], 0.0f);
+      }
+      if constexpr (MASK) {
+        v0[q] = em0[q] > 0.0f ? v0[q] : 0.0f;
+        v1[q] = em1[q] > 0.0f ? v1[q] : 0.0f;
+      }
+    }
+    for (int q = 0; q < 2; ++q) {
+      const uint16_t a = to_bf16_bits(v0[2 * q]), b = to_bf16_bits(v0[2 * q + 1]);
+      const uint16_t c = to_bf16_bits(v1[2 * q]), d = to_bf16_bits(v1[2 * q + 1]);
+      w0[q] = (uint32_t)a | ((uint32_t)b << 16);
+      w1[q] = (uint32_t)c | ((uint32_t)d << 16);
+      if constexpr (BM == 1) {
+        nib0 |= ((widen(a) > 0.0f ? 1u : 0u) | (widen(b) > 0.0f ? 2u : 0u)) << (2 * q);
+        nib1 |= ((widen(c) > 0.0f ? 1u : 0u) | (widen(d) > 0.0f ? 2u : 0u)) << (2 * q);
+      }
+    }
+    if constexpr (BM == 1) {
+      bits_store(obits, ldm, r, nt + 4 * g4, nib0);
+      bits_store(obits, ldm, r, nt + 16 + 4 * g4, nib1);
+    }
+    const bool odd = g4 & 1;
+    uint32_t out[4];
+    for (int q = 0; q < 2; ++q) {
+      const uint32_t mine = odd ? w0[q] : w1[q];  // the half the partner stores
+      const auto x = __builtin_amdgcn_permlane16_swap(mine, mine, false, false);
+      // one of the two results is this lane's own value, the other the partner's
+      const uint32_t theirs = x[0] ^ x[1] ^ mine;
+      if (odd) {
+        out[q] = theirs;
+        out[2 + q] = w1[q];
+      } else {
+        out[q] = w0[q];
+        out[2 + q] = theirs;
+      }
+    }
+    const int col = odd ? nt + 16 + 4 * (g4 - 1) : nt + 4 * g4;
+    __builtin_memcpy(C + r * ldc + col, out, 16);
   }
 };
 
