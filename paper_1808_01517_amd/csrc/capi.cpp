@@ -1047,14 +1047,14 @@ dlm_status dlm_lsc_bwd_io(const dlm_lsc_plan *p, const void *a_in, int C, const 
                           const void *da_out, void *da_in, float *dW, float *dbias, int64_t V, int relu_flags,
                           int io_flags, const uint16_t *relu_bits, dlm_lsc_form form, void *ws, size_t ws_bytes,
                           dlm_precision prec, void *stream) {
-  if (relu_bits && (form != DLM_LSC_FOLDED || !(relu_flags & DLM_RELU_IN) || (C * p->K_in) % 16 != 0))
-    return fail(DLM_EINVAL, "ReLU bits need the folded form, DLM_RELU_IN and C*K_in a multiple of 16");
   if (io_flags == 0 && !relu_bits)
     return dlm_lsc_bwd(p, static_cast<const float *>(a_in), C, W, O, static_cast<const float *>(a_out),
                        static_cast<const float *>(da_out), static_cast<float *>(da_in), dW, dbias, V, relu_flags, form,
                        ws, ws_bytes, prec, stream);
   dlm_status s = lsc_check(p, C, O, V, prec);
   if (s != DLM_OK) return s;
+  if (relu_bits && (form != DLM_LSC_FOLDED || !(relu_flags & DLM_RELU_IN) || (C * p->K_in) % 16 != 0))
+    return fail(DLM_EINVAL, "ReLU bits need the folded form, DLM_RELU_IN and C*K_in a multiple of 16");
   if ((s = io_check(p, C, O, io_flags, form, prec, a_in, da_in, a_out, da_out)) != DLM_OK) return s;
   if (!ws) return fail(DLM_EINVAL, "workspace is NULL");
   if (relu_flags & ~(DLM_RELU_OUT | DLM_RELU_IN)) return fail(DLM_EINVAL, "unknown relu flags 0x%x", relu_flags);

@@ -86,3 +86,47 @@ def test_status_codes(L):
     assert lib.dlm_lsc_fwd(None, None, 3, None, None, 3, None, 10, 0, 0, None, 0, 0, None) == L.DLM_EINVAL
     assert lib.dlm_mse_fwd_bwd(None, None, 0, None, None, None, 0, None) == L.DLM_EINVAL
     assert lib.dlm_adam_step(None, None, None, None, 5, 1e-3, 0.9, 0.999, 1e-8, 0, None) == L.DLM_EINVAL
+
+
+def _header_param_counts():
+    txt = open(os.path.join(ROOT, "include", "delimit.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    out = {}
+    for name, params in re.findall(r"\b(dlm_[a-z0-9_]+)\s*\(([^;{}]*?)\)\s*;", txt, flags=re.S):
+        params = params.strip()
+        out[name] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
+def test_header_parameter_counts_match_bindings(L):
+    """Every declaration's parameter count equals its ctypes binding's, so a
+    signature change on one side cannot go unnoticed."""
+    counts = _header_param_counts()
+    assert set(counts) == set(L.SIGNATURES), set(counts) ^ set(L.SIGNATURES)
+    bad = {n: (c, len(L.SIGNATURES[n][1])) for n, c in counts.items() if c != len(L.SIGNATURES[n][1])}
+    assert not bad, bad
+
+
+def test_relu_bits_host_helpers(L):
+    import torch
+
+    import paper_1808_01517_amd as dl
+    a = torch.empty((7, 32, 45))
+    b = dl.relu_bits_like(a)
+    assert b.dtype == torch.int16 and tuple(b.shape) == (7, 90)
+    assert tuple(dl.relu_bits_like(torch.empty((0, 64, 45))).shape) == (0, 180)
+    with pytest.raises(ValueError):  # 3 x 45 entries per row
+        dl.relu_bits_like(torch.empty((4, 3, 45)))
+    with pytest.raises(ValueError):  # bits must live on the device
+        dl._bits_dev(b, 7, 32 * 45, "relu_bits")
+    assert dl._bits_dev(None, 7, 32 * 45, "relu_bits") is None
+    # the entry points validate their plan before touching the device
+    lib = L.lib()
+    assert lib.dlm_lsc_fwd_io(None, None, 32, None, None, 3, None, 10, 1, 0, None, 1, None, 0, 0, None) == L.DLM_EINVAL
+    assert lib.dlm_lsc_bwd_io(None, None, 32, None, 3, None, None, None, None, None, 10, 2, 0, None, 1, None, 0, 0,
+                              None) == L.DLM_EINVAL
+    # a bits pointer with no plan: rejected before anything is dereferenced
+    words = (C.c_uint16 * 8)()
+    assert lib.dlm_lsc_fwd_io(None, None, 3, None, None, 32, None, 10, 1, 0, words, 1, None, 0, 0, None) == L.DLM_EINVAL
+    assert lib.dlm_lsc_bwd_io(None, None, 32, None, 3, None, None, None, None, None, 10, 2, 0, words, 1, None, 0, 0,
+                              None) == L.DLM_EINVAL
