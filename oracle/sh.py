@@ -106,6 +106,16 @@ def fit_matrix(B: np.ndarray, sh_order: int, lb_lambda: float) -> np.ndarray:
     return np.linalg.solve(B.T @ B + lb_lambda * L, B.T)
 
 
+def has_fit(B: np.ndarray, sh_order: int, lb_lambda: float) -> bool:
+    """Whether the regularised normal matrix B^T B + lambda L has full rank
+    K, i.e. the least-squares fit of Signal2SH exists.  SH2Signal needs only
+    the basis (evaluation on any N resampled directions, Sec. 2.2), so a
+    table with fewer directions than coefficients at lambda = 0 is fine for
+    it."""
+    A = B.T @ B + lb_lambda * np.diag(lb_penalty(sh_order))
+    return int(np.linalg.matrix_rank(A)) == A.shape[0]
+
+
 def group_shells(bvals: np.ndarray, b0_max: float = 50.0, rel_tol: float = 0.05):
     """Drop b0 volumes (b < b0_max) and group the rest into shells.
 
@@ -140,7 +150,10 @@ class SHPlan:
         self.shell_idx, self.shell_b = group_shells(bvals, b0_max, rel_tol)
         bvecs = np.asarray(bvecs, dtype=np.float64)
         self.B = [basis_at(sh_order, bvecs[idx]) for idx in self.shell_idx]
-        self.P = [fit_matrix(B, sh_order, lb_lambda) for B in self.B]
+        # P_s exists only where the fit does; without it the plan evaluates
+        # only (sh2signal and its adjoint) and signal2sh raises
+        self.has_fit = all(has_fit(B, sh_order, lb_lambda) for B in self.B)
+        self.P = [fit_matrix(B, sh_order, lb_lambda) for B in self.B] if self.has_fit else None
         self.dirs = [idx.shape[0] for idx in self.shell_idx]
 
     @property
@@ -151,6 +164,8 @@ class SHPlan:
 def signal2sh(plan: SHPlan, x: np.ndarray) -> np.ndarray:
     """c[v, s, :] = P_s x[v, s-block] for b0-normalised signal x of shape
     (V, sum N_s) in shell-major order; returns (V, S, K)."""
+    if plan.P is None:
+        raise np.linalg.LinAlgError("the plan's regularised normal matrix is singular: no fit")
     V = x.shape[0]
     out = np.empty((V, plan.n_shells, plan.K))
     off = 0
@@ -168,6 +183,8 @@ def sh2signal(plan: SHPlan, c: np.ndarray) -> np.ndarray:
 
 def signal2sh_adjoint(plan: SHPlan, dc: np.ndarray) -> np.ndarray:
     """dx = P_s^T dc per shell (gradient of Signal2SH w.r.t. its input)."""
+    if plan.P is None:
+        raise np.linalg.LinAlgError("the plan's regularised normal matrix is singular: no fit")
     return np.concatenate([dc[:, s, :] @ P for s, P in enumerate(plan.P)], axis=1)
 
 

@@ -223,3 +223,42 @@ def test_transform_adjoints(fn, adj, shape_in, shape_out):
     lhs = np.sum(fn(plan, u) * w)
     rhs = np.sum(u * adj(plan, w))
     assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
+
+
+def test_fit_exists_unless_normal_matrix_is_rank_deficient():
+    # At lambda = 0 the normal matrix B^T B has rank min(N, K) for directions
+    # in general position, so the fit needs N >= K.  For lambda > 0 the
+    # penalty covers every l > 0 and only Y_00 (a nonzero constant, never in
+    # the null space of B) is unpenalised: a fit exists for any N >= 1.
+    g = _table(30, 10)
+    assert not sh.has_fit(sh.basis_at(8, g), 8, 0.0)          # N = 30 < K = 45
+    assert sh.has_fit(sh.basis_at(8, g), 8, 0.006)
+    assert sh.has_fit(sh.basis_at(4, g), 4, 0.0)              # N = 30 >= K = 15
+    assert sh.has_fit(sh.basis_at(8, g[:1]), 8, 0.006)        # one direction
+    plan = sh.SHPlan(g, np.full(30, 1000.0), 8, 0.0)
+    assert not plan.has_fit and plan.P is None
+    with pytest.raises(np.linalg.LinAlgError):
+        sh.signal2sh(plan, np.ones((1, 30)))
+    with pytest.raises(np.linalg.LinAlgError):
+        sh.signal2sh_adjoint(plan, np.ones((1, 1, 45)))
+
+
+def test_evaluation_only_plan_evaluates_closed_forms():
+    # SH2Signal onto 30 directions at order 8 (no fit): the l = 2, m = 0
+    # coefficient alone gives the textbook sqrt(5/(16 pi)) (3 z^2 - 1), and
+    # the l = 8 block filled with Y_8m(v) gives the addition theorem's
+    # (2l+1)/(4 pi) P_8(g . v) at every direction g, independent of convention.
+    g = _table(30, 11)
+    plan = sh.SHPlan(g, np.full(30, 1000.0), 8, 0.0)
+    gn = g / np.linalg.norm(g, axis=1, keepdims=True)
+    ls, ms = sh.degree_order(8)
+    c = np.zeros((1, 1, 45))
+    c[0, 0, int(np.flatnonzero((ls == 2) & (ms == 0))[0])] = 1.0
+    expect = math.sqrt(5 / (16 * math.pi)) * (3 * gn[:, 2] ** 2 - 1)
+    assert np.abs(sh.sh2signal(plan, c)[0] - expect).max() < 1e-14
+    v = np.array([[0.3, -0.5, 0.81]])
+    v /= np.linalg.norm(v)
+    c = np.zeros((1, 1, 45))
+    c[0, 0, ls == 8] = sh.basis_at(8, v)[0, ls == 8]
+    expect = 17 / (4 * math.pi) * sps.eval_legendre(8, gn @ v[0])
+    assert np.abs(sh.sh2signal(plan, c)[0] - expect).max() < 1e-12
