@@ -89,7 +89,14 @@ typedef struct dlm_sh_plan dlm_sh_plan;
  * ordered by increasing b, volumes within a shell in table order.
  * Signal arrays at the ABI are shell-major: [V][N_dw] = shell 0's N_0
  * values, then shell 1's ...  *out receives the plan (free with
- * dlm_sh_plan_destroy). */
+ * dlm_sh_plan_destroy).
+ * SH2Signal evaluates the basis on any table (Sec. 2.2: signals on N
+ * resampled directions), so a shell whose regularised normal matrix
+ * B_s^T B_s + lambda L is singular (e.g. fewer directions than K at
+ * lambda = 0) does not fail creation: the plan then evaluates only
+ * (dlm_sh2signal_fwd/bwd, dlm_sh2signal_mse_fwd_bwd), and every call that
+ * needs P_s (dlm_signal2sh_fwd/bwd, dlm_signal2sh_fwd_raw, P copies of
+ * dlm_sh_plan_matrices) returns DLM_ESINGULAR. */
 dlm_status dlm_sh_plan_create(const double *bvecs, const double *bvals, int64_t n, int sh_order,
                               double lb_lambda, double b0_max, double shell_rel_tol, dlm_sh_plan **out);
 /* n_shells, K and total diffusion-weighted count N_dw (any may be NULL). */
@@ -98,11 +105,18 @@ dlm_status dlm_sh_plan_info(const dlm_sh_plan *plan, int *n_shells, int *K, int6
  * index into the creation table of each of its n_dirs volumes. */
 dlm_status dlm_sh_plan_shell(const dlm_sh_plan *plan, int shell, int64_t *n_dirs, double *b,
                              int64_t *volume_index);
-/* Host float64 copies of B_s [N_s][K] and P_s [K][N_s] (either may be NULL). */
+/* Host float64 copies of B_s [N_s][K] and P_s [K][N_s] (either may be NULL;
+ * B is copied before P is refused on a plan without a fit). */
 dlm_status dlm_sh_plan_matrices(const dlm_sh_plan *plan, int shell, double *B, double *P);
+/* DLM_OK when every shell has its fit P_s (Signal2SH is available),
+ * DLM_ESINGULAR (message names the first singular shell) when the plan
+ * evaluates only. */
+dlm_status dlm_sh_plan_fit_status(const dlm_sh_plan *plan);
 /* Replace the directions (same n and b-values as at creation, e.g. a fresh
  * per-scan distortion) and rebuild every table in float64; the upload is
- * ordered on `stream`, so calls already queued on it use the old tables. */
+ * ordered on `stream`, so calls already queued on it use the old tables.
+ * A plan with a fit keeps one: if the new table's fit is singular the call
+ * returns DLM_ESINGULAR and leaves the plan unchanged. */
 dlm_status dlm_sh_plan_update_gradients(dlm_sh_plan *plan, const double *bvecs, void *stream);
 void dlm_sh_plan_destroy(dlm_sh_plan *plan);
 

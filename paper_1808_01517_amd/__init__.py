@@ -115,8 +115,15 @@ class SHPlan:
         check(lib().dlm_sh_plan_create(dptr(bv), dptr(bl), bv.shape[0], int(sh_order), float(lb_lambda),
                                        float(b0_max), float(shell_rel_tol), C.byref(h)))
         self._h = h
+        # bound now: __del__ may run during interpreter teardown, when module
+        # globals such as lib() are already gone
+        self._destroy = lib().dlm_sh_plan_destroy
         self.sh_order = int(sh_order)
         self.n_total = bv.shape[0]
+        # False for an evaluation-only plan (a shell's fit is singular, e.g.
+        # fewer directions than coefficients at lb_lambda = 0): SH2Signal and
+        # its adjoint work, Signal2SH calls raise DelimitError
+        self.has_fit = lib().dlm_sh_plan_fit_status(h) == _lib.DLM_OK
         S, K, n = C.c_int(), C.c_int(), C.c_int64()
         check(lib().dlm_sh_plan_info(h, C.byref(S), C.byref(K), C.byref(n)))
         self.n_shells, self.K, self.n_dw = S.value, K.value, n.value
@@ -133,8 +140,13 @@ class SHPlan:
         return self._h
 
     def matrices(self, shell: int):
+        """(B_s [N_s][K], P_s [K][N_s]) in float64; P_s is None on an
+        evaluation-only plan."""
         n = self.shells[shell][0]
         B = np.zeros((n, self.K))
+        if not self.has_fit:
+            check(lib().dlm_sh_plan_matrices(self._h, shell, dptr(B), None))
+            return B, None
         P = np.zeros((self.K, n))
         check(lib().dlm_sh_plan_matrices(self._h, shell, dptr(B), dptr(P)))
         return B, P
@@ -145,11 +157,13 @@ class SHPlan:
             raise ValueError("update_gradients needs the same number of volumes")
         st = C.c_void_p(stream if stream is not None else torch.cuda.current_stream().cuda_stream)
         check(lib().dlm_sh_plan_update_gradients(self._h, dptr(bv), st))
+        self.has_fit = lib().dlm_sh_plan_fit_status(self._h) == _lib.DLM_OK
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().dlm_sh_plan_destroy(h)
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and h.value and destroy is not None:
+            destroy(h)
             self._h = None
 
 
@@ -165,6 +179,7 @@ class LSCPlan:
         check(lib().dlm_lsc_plan_create(dptr(g), g.shape[0], int(sh_order_in), int(sh_order_out), arr, len(ks),
                                         float(angular_distance), float(lb_lambda), C.byref(h)))
         self._h = h
+        self._destroy = lib().dlm_lsc_plan_destroy  # see SHPlan.__init__
         T, Ki, Ko, m = C.c_int(), C.c_int(), C.c_int(), C.c_int64()
         check(lib().dlm_lsc_plan_info(h, C.byref(T), C.byref(Ki), C.byref(Ko), C.byref(m)))
         self.T, self.K_in, self.K_out, self.m = T.value, Ki.value, Ko.value, m.value
@@ -184,8 +199,9 @@ class LSCPlan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().dlm_lsc_plan_destroy(h)
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and h.value and destroy is not None:
+            destroy(h)
             self._h = None
 
 
@@ -215,9 +231,13 @@ _ws_cache: dict = {}
 
 
 def _default_ws(plan: LSCPlan, C_in: int, O: int, V: int, prec: int, device, form) -> Workspace:
-    """A shared workspace (resample form: up to 65536 voxels per pass)."""
+    """A workspace shared by the calls on one stream (resample form: up to
+    65536 voxels per pass).  Keyed by device and stream: calls on one stream
+    run in order, so they may share scratch; calls on different streams get
+    their own.  Growing it frees the old buffer through torch's caching
+    allocator, which reuses it only after the stream's queued work."""
     need = lsc_workspace_bytes(plan, C_in, O, min(max(V, 1), 1 << 16), prec, form)
-    key = str(device)
+    key = (str(device), torch.cuda.current_stream(device).cuda_stream)
     ws = _ws_cache.get(key)
     if ws is None or ws.nbytes < need:
         ws = Workspace(need, device)

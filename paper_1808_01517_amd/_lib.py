@@ -33,6 +33,7 @@ SIGNATURES = {
     "dlm_sh_plan_info": (_st, [_p, C.POINTER(_int), C.POINTER(_int), C.POINTER(_i64)]),
     "dlm_sh_plan_shell": (_st, [_p, _int, C.POINTER(_i64), C.POINTER(_dbl), C.POINTER(_i64)]),
     "dlm_sh_plan_matrices": (_st, [_p, _int, _dp, _dp]),
+    "dlm_sh_plan_fit_status": (_st, [_p]),
     "dlm_sh_plan_update_gradients": (_st, [_p, _dp, _p]),
     "dlm_sh_plan_destroy": (None, [_p]),
     "dlm_signal2sh_fwd": (_st, [_p, _p, _p, _i64, _int, _p]),

@@ -39,6 +39,20 @@ dlm_status ok() {
   return DLM_OK;
 }
 
+}  // namespace
+
+dlm_status dlm::report(dlm_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+namespace {
+
 dlm_status launched(int rc) {
   if (rc == 0) return DLM_OK;
   if (rc == -3)  // every launcher's code for an operand layout it does not take
@@ -103,6 +117,11 @@ struct dlm_sh_plan {
   std::vector<int64_t> dirs, offs;
   std::vector<std::vector<double>> B, P;  // host float64, B_s [N_s][K], P_s [K][N_s]
   bool uniform = true;
+  // Whether every shell's fit (B^T B + lambda L) is positive definite.  A
+  // plan without one still evaluates the basis (SH2Signal and its adjoint);
+  // its P tables are zeros and every call that would read them fails.
+  bool fit_ok = true;
+  int singular_shell = -1;
   // device, all shells back to back: P [S][K][N], Pt [S][N][K], B [S][N][K], Bt [S][K][N]
   DevMat dP, dPt, dB, dBt;
   // the same four tables in MFMA fragment order for the per-shell kernel
@@ -149,11 +168,27 @@ dlm_status sh_build_tables(dlm_sh_plan *p, const double *bvecs) {
     p->B[s].resize(size_t(n) * p->K);
     p->P[s].resize(size_t(n) * p->K);
     sh_basis_unit(p->L, u.data(), n, p->B[s].data());
-    if (!fit_from_basis(p->L, p->B[s].data(), n, p->lambda, p->P[s].data()))
-      return fail(DLM_ESINGULAR, "shell %d (b=%g): normal matrix of %lld directions at order %d is singular", s,
-                  p->shell_b[s], (long long)n, p->L);
   }
+  // SH2Signal needs only the basis (evaluation on any table, Sec. 2.2); the
+  // fit exists only where the regularised normal matrix is positive definite
+  // (e.g. not for fewer directions than coefficients at lambda = 0).
+  p->fit_ok = true;
+  p->singular_shell = -1;
+  for (int s = 0; s < p->S; ++s)
+    if (!fit_from_basis(p->L, p->B[s].data(), p->dirs[s], p->lambda, p->P[s].data())) {
+      std::fill(p->P[s].begin(), p->P[s].end(), 0.0);
+      if (p->fit_ok) p->singular_shell = s;
+      p->fit_ok = false;
+    }
   return DLM_OK;
+}
+
+dlm_status no_fit(const dlm_sh_plan *p) {
+  const int s = p->singular_shell;
+  return fail(DLM_ESINGULAR,
+              "shell %d (b=%g): the normal matrix of %lld directions at order %d and lambda %g is singular; "
+              "this plan evaluates the basis (SH2Signal) only",
+              s, p->shell_b[s], (long long)p->dirs[s], p->L, p->lambda);
 }
 
 dlm_status sh_upload(dlm_sh_plan *p, hipStream_t st) {
@@ -398,18 +433,31 @@ dlm_status dlm_sh_plan_matrices(const dlm_sh_plan *p, int shell, double *B, doub
   if (!p) return fail(DLM_EINVAL, "plan is NULL");
   if (shell < 0 || shell >= p->S) return fail(DLM_EINVAL, "shell %d out of range [0, %d)", shell, p->S);
   if (B) std::copy(p->B[shell].begin(), p->B[shell].end(), B);
-  if (P) std::copy(p->P[shell].begin(), p->P[shell].end(), P);
+  if (P) {
+    if (!p->fit_ok) return no_fit(p);
+    std::copy(p->P[shell].begin(), p->P[shell].end(), P);
+  }
   return ok();
+}
+
+dlm_status dlm_sh_plan_fit_status(const dlm_sh_plan *p) {
+  if (!p) return fail(DLM_EINVAL, "plan is NULL");
+  return p->fit_ok ? ok() : no_fit(p);
 }
 
 dlm_status dlm_sh_plan_update_gradients(dlm_sh_plan *p, const double *bvecs, void *stream) {
   if (!p || !bvecs) return fail(DLM_EINVAL, "plan or bvecs is NULL");
   auto saved_B = p->B;
   auto saved_P = p->P;
+  const bool had_fit = p->fit_ok;
+  const int saved_shell = p->singular_shell;
   dlm_status s = sh_build_tables(p, bvecs);
+  if (s == DLM_OK && had_fit && !p->fit_ok) s = no_fit(p);  // a plan with a fit keeps one
   if (s != DLM_OK) {
     p->B = saved_B;
     p->P = saved_P;
+    p->fit_ok = had_fit;
+    p->singular_shell = saved_shell;
     return s;
   }
   s = sh_upload(p, (hipStream_t)stream);
@@ -445,6 +493,7 @@ dlm_status sh_apply(const dlm_sh_plan *p, const float *in, float *out, int64_t V
   if (!p) return fail(DLM_EINVAL, "plan is NULL");
   if (V < 0) return fail(DLM_EINVAL, "V must be >= 0");
   if (prec != DLM_FP32 && prec != DLM_BF16) return fail(DLM_EINVAL, "unknown precision %d", int(prec));
+  if ((op == ShOp::S2shFwd || op == ShOp::S2shBwd) && !p->fit_ok) return no_fit(p);
   if (V == 0) return ok();
   if (!in || !out) return fail(DLM_EINVAL, "null device pointer");
   const int K = p->K, S = p->S;
@@ -530,6 +579,7 @@ dlm_status dlm_signal2sh_fwd_raw(const dlm_sh_plan *p, const float *raw, float *
   if (V < 0) return fail(DLM_EINVAL, "V must be >= 0");
   if (prec != DLM_FP32 && prec != DLM_BF16) return fail(DLM_EINVAL, "unknown precision %d", int(prec));
   if (p->n_b0 == 0) return fail(DLM_EINVAL, "the gradient table has no b=0 volume to normalise by");
+  if (!p->fit_ok) return no_fit(p);
   if (V == 0) return ok();
   if (!raw || !c || !ws) return fail(DLM_EINVAL, "null device pointer");
   if (ws_bytes < dlm_signal2sh_raw_workspace_bytes(V)) return fail(DLM_EWORKSPACE, "workspace too small");

@@ -217,6 +217,11 @@ int launch_sum_partials(const float *part, int splits, int64_t n, float *out, vo
 int launch_lsc_unfold(const float *dTw, const float *Q, const float *pm1, int C, int O, int T, int Ki, int Ko,
                       float *dW, float *db, void *stream);
 
+// ----------------------------------------------------------- status text
+// Set the thread's dlm_last_error() text and return s (for library sources
+// other than the C ABI file).
+dlm_status report(dlm_status s, const char *fmt, ...);
+
 // ------------------------------------------------------- timing support
 // When enabled, TimedScope brackets a launch with a HIP event pair on its
 // stream and files it under `tag` with its algorithmic bytes and flops.

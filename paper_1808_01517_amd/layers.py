@@ -109,6 +109,8 @@ class SH2Signal(nn.Module):
     def __init__(self, sh_order: int, gradients, bvals=None, precision="fp32"):
         super().__init__()
         g, b = _table(gradients, bvals)
+        # evaluation needs the basis only: any table works, also one with
+        # fewer directions than coefficients (the plan then has no fit)
         self.plan = SHPlan(g, b, sh_order, 0.0)
         self.precision = precision
 

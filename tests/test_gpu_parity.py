@@ -1,8 +1,9 @@
 """GPU parity of the HIP layers against the FP64 oracle.
 
-Norm-wise relative error ||out - ref||_F / ||ref||_F per output tensor:
-FP32 form <= 1e-5, BF16 form <= 2e-2 (the tolerances the workloads state).
-Sizes span several tiles with ragged tails (V not a multiple of any tile).
+Each output is held to a norm-wise bound (FP32 form <= 1e-5, BF16 form
+<= 2e-2, the tolerances the workloads state) and a per-voxel bound (FP32
+<= 1e-4, BF16 <= 5e-2; see parity_util).  Sizes span several tiles with
+ragged tails (V not a multiple of any tile).
 """
 import numpy as np
 import pytest
@@ -16,16 +17,11 @@ from oracle import lsc as olsc
 from oracle import sh as osh
 from oracle import stack as ostack
 
+from parity_util import TOL, check, fmt, rel
+
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": 1e-5, "bf16": 2e-2}
 DEV = "cuda:0"
-
-
-def rel(out, ref):
-    out = out.detach().double().cpu().numpy() if isinstance(out, torch.Tensor) else np.asarray(out, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
-    return float(np.linalg.norm(out - ref) / max(np.linalg.norm(ref), 1e-300))
 
 
 def cuda(a):
@@ -52,19 +48,21 @@ def test_sh_transforms(prec, which, c1_acq, c2_acq):
     batch = dg.stick_ball_batch(acq, V, 3, 20.0, dg.rng_for(11, 2, 0))
     x = batch.x
     xg = cuda(x)
+    errs = {}
     c = dl.signal2sh_fwd(plan, xg, precision=prec)
     c_ref = osh.signal2sh(oplan, x.astype(np.float32).astype(np.float64))
-    assert rel(c, c_ref) <= TOL[prec]
+    check("c", c, c_ref, prec, errs)
     xr = dl.sh2signal_fwd(plan, c, precision=prec)
     xr_ref = osh.sh2signal(oplan, c.double().cpu().numpy())
-    assert rel(xr, xr_ref) <= TOL[prec]
+    check("x", xr, xr_ref, prec, errs)
     rng = np.random.default_rng(3)
     dc = rng.standard_normal(c_ref.shape)
     dx = dl.signal2sh_bwd(plan, cuda(dc), precision=prec)
-    assert rel(dx, osh.signal2sh_adjoint(oplan, dc.astype(np.float32))) <= TOL[prec]
+    check("dx", dx, osh.signal2sh_adjoint(oplan, dc.astype(np.float32)), prec, errs)
     dxx = rng.standard_normal(x.shape)
     dcc = dl.sh2signal_bwd(plan, cuda(dxx), precision=prec)
-    assert rel(dcc, osh.sh2signal_adjoint(oplan, dxx.astype(np.float32))) <= TOL[prec]
+    check("dc", dcc, osh.sh2signal_adjoint(oplan, dxx.astype(np.float32)), prec, errs)
+    print(f"[parity] sh transforms {which} {prec}: " + fmt(errs), flush=True)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
@@ -88,11 +86,12 @@ def test_sh_transforms_across_orders(prec, L, c2_acq):
     dc = dl.sh2signal_bwd(plan, cuda(dx), precision=prec)
     dcc = rng.standard_normal(c_ref.shape)
     dxx = dl.signal2sh_bwd(plan, cuda(dcc), precision=prec)
-    errs = {"c": rel(c, c_ref), "x": rel(xr, xr_ref),
-            "dc": rel(dc, osh.sh2signal_adjoint(oplan, dx.astype(np.float32))),
-            "dx": rel(dxx, osh.signal2sh_adjoint(oplan, dcc.astype(np.float32)))}
-    print(f"[parity] sh order {L} {prec}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
-    assert all(v <= TOL[prec] for v in errs.values()), errs
+    errs = {}
+    check("c", c, c_ref, prec, errs)
+    check("x", xr, xr_ref, prec, errs)
+    check("dc", dc, osh.sh2signal_adjoint(oplan, dx.astype(np.float32)), prec, errs)
+    check("dx", dxx, osh.signal2sh_adjoint(oplan, dcc.astype(np.float32)), prec, errs)
+    print(f"[parity] sh order {L} {prec}: " + fmt(errs), flush=True)
 
 
 def _lsc_case(C, O, L_in, L_out, ks, m_dirs, V, seed):
@@ -120,15 +119,17 @@ def test_lsc_forward_backward(prec, case, relu, form):
     out_ref, z = olsc.lsc_forward(oplan, a, W, b, relu)
     ag, Wg, bg = cuda(a), cuda(W), cuda(b)
     out = dl.lsc_fwd(plan, ag, Wg, bg, relu=relu, precision=prec, form=form)
-    assert rel(out, out_ref) <= TOL[prec]
+    errs = {}
+    check("out", out, out_ref, prec, errs)
     da_out = np.random.default_rng(9).standard_normal(out_ref.shape).astype(np.float32).astype(np.float64)
     # mask from the GPU's own forward output so both sides use the same ReLU pattern
     z_mask = out.double().cpu().numpy() if relu else z
     da_ref, dW_ref, db_ref = olsc.lsc_backward(oplan, a, W, z_mask, da_out, relu)
     da, dW, db = dl.lsc_bwd(plan, ag, Wg, cuda(da_out), a_out=out, relu=relu, precision=prec, form=form)
-    assert rel(da, da_ref) <= TOL[prec]
-    assert rel(dW, dW_ref) <= TOL[prec]
-    assert rel(db, db_ref) <= TOL[prec]
+    check("da", da, da_ref, prec, errs)
+    check("dW", dW, dW_ref, prec, errs, kind="sum")
+    check("db", db, db_ref, prec, errs, kind="sum")
+    print(f"[parity] lsc {C}->{O} L{L_in}->{L_out} {prec} {form} relu={relu}: " + fmt(errs), flush=True)
 
 
 @pytest.mark.parametrize("form", ["resample", "folded"])
@@ -144,9 +145,9 @@ def test_lsc_backward_masks_input_gradient(prec, form, case):
     _, z = olsc.lsc_forward(oplan, a, W, b, False)
     da_ref, dW_ref, db_ref = olsc.lsc_backward(oplan, a, W, z, da_out, False)
     da, dW, db = dl.lsc_bwd(plan, cuda(a), cuda(W), cuda(da_out), relu_in=True, precision=prec, form=form)
-    assert rel(da, da_ref * (a > 0)) <= TOL[prec]
-    assert rel(dW, dW_ref) <= TOL[prec]
-    assert rel(db, db_ref) <= TOL[prec]
+    check("da", da, da_ref * (a > 0), prec)
+    check("dW", dW, dW_ref, prec, kind="sum")
+    check("db", db, db_ref, prec, kind="sum")
     masked = da.cpu().numpy()[a <= 0]
     assert np.all(masked == 0.0)
 
@@ -174,7 +175,6 @@ def test_lsc_bf16_activation_storage(case):
                        out_dtype=half if out_half else torch.float32)
     assert torch.equal(out_h, out_f.to(out_h.dtype))
     out_ref, _ = olsc.lsc_forward(oplan, a64, W, b, True)
-    assert rel(out_h.float(), out_ref) <= TOL["bf16"]
     da = cuda(np.random.default_rng(11).standard_normal((V, O, plan.K_out)))
     da_h = da.to(half) if out_half else da
     da_f = da_h.float()
@@ -185,10 +185,12 @@ def test_lsc_bf16_activation_storage(case):
     assert torch.equal(dW_h, dW_f) and torch.equal(db_h, db_f)
     _, z = olsc.lsc_forward(oplan, a64, W, b, False)
     da_ref, dW_ref, db_ref = olsc.lsc_backward(oplan, a64, W, z, da_f.double().cpu().numpy(), False)
-    errs = {"out": rel(out_h.float(), out_ref), "da_in": rel(gi_h.float(), da_ref * (a64 > 0)),
-            "dW": rel(dW_h, dW_ref), "db": rel(db_h, db_ref)}
-    print(f"[parity] lsc bf16 storage C={C} O={O}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
-    assert all(v <= TOL["bf16"] for v in errs.values()), errs
+    errs = {}
+    check("out", out_h.float(), out_ref, "bf16", errs)
+    check("da_in", gi_h.float(), da_ref * (a64 > 0), "bf16", errs)
+    check("dW", dW_h, dW_ref, "bf16", errs, kind="sum")
+    check("db", db_h, db_ref, "bf16", errs, kind="sum")
+    print(f"[parity] lsc bf16 storage C={C} O={O}: " + fmt(errs), flush=True)
 
 
 def test_lsc_bf16_activation_storage_rejects_unsupported():
@@ -241,7 +243,9 @@ def test_lsc_chunked_workspace_matches_single_pass():
     assert torch.equal(r1[0], r2[0])
     assert rel(r1[1], r2[1].double().cpu().numpy()) < 1e-6
     ref = olsc.lsc_backward(oplan, a, W, o1.double().cpu().numpy(), g.double().cpu().numpy(), True)
-    assert rel(r1[1], ref[1]) <= 1e-5 and rel(r1[2], ref[2]) <= 1e-5
+    check("da", r1[0], ref[0], "fp32")
+    check("dW", r1[1], ref[1], "fp32", kind="sum")
+    check("db", r1[2], ref[2], "fp32", kind="sum")
 
 
 @pytest.mark.parametrize("form", ["resample", "folded"])
@@ -264,6 +268,7 @@ def test_mse_and_adam():
     l_ref, g_ref = ostack.mse(p.astype(np.float32).astype(np.float64), t.astype(np.float32).astype(np.float64))
     assert abs(loss.item() - l_ref) / l_ref < 1e-5
     assert rel(dp, g_ref) < 1e-6
+    check("dp", dp.reshape(-1, 1), g_ref.reshape(-1, 1), "fp32")
     w = rng.standard_normal(1000)
     g = rng.standard_normal(1000)
     wg, gg = cuda(w), cuda(g)
@@ -309,7 +314,8 @@ def test_c2_stack_forward_backward(prec, form, mask_at, c2_acq):
     loss, dxhat = dl.mse_fwd_bwd(xhat, cuda(tgt))
     # oracle with the GPU's ReLU pattern (masks from the GPU's activations)
     xhat_ref, cache = net.forward(x)
-    assert rel(xhat, xhat_ref) <= TOL[prec]
+    errs = {}
+    check("xhat", xhat, xhat_ref, prec, errs)
     gpu_z = [a.double().cpu().numpy() for a in acts[1:]]
     cache = (cache[0], [gz if L.relu else z for gz, z, L in zip(gpu_z, cache[1], olayers)])
     l_ref, dxh_ref = ostack.mse(xhat_ref, tgt)
@@ -325,11 +331,13 @@ def test_c2_stack_forward_backward(prec, form, mask_at, c2_acq):
             kw = dict(relu=False, relu_in=k > 0 and layers[k - 1][3])
         gcur, dWs[k], dbs[k] = dl.lsc_bwd(p, acts[k], Wk, gcur, a_out=acts[k + 1], precision=prec, form=form, **kw)
     dx = dl.signal2sh_bwd(plan, gcur, precision=prec)
-    errs = {"xhat": rel(xhat, xhat_ref), "loss": abs(loss.item() - l_ref) / l_ref, "dx": rel(dx, dx_ref)}
+    errs["loss"] = abs(loss.item() - l_ref) / l_ref
+    check("dx", dx, dx_ref, prec, errs)
     for k in range(len(layers)):
-        errs[f"dW{k}"], errs[f"db{k}"] = rel(dWs[k], dWs_ref[k]), rel(dbs[k], dbs_ref[k])
-    print(f"[parity] c2 stack {prec} {form} mask@{mask_at}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
-    assert all(v <= TOL[prec] for v in errs.values()), errs
+        check(f"dW{k}", dWs[k], dWs_ref[k], prec, errs, kind="sum")
+        check(f"db{k}", dbs[k], dbs_ref[k], prec, errs, kind="sum")
+    print(f"[parity] c2 stack {prec} {form} mask@{mask_at}: " + fmt(errs), flush=True)
+    assert errs["loss"] <= TOL[prec], errs
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
@@ -340,7 +348,7 @@ def test_folded_matches_resample_form(prec):
     ag, Wg, bg = cuda(a), cuda(W), cuda(b)
     o1 = dl.lsc_fwd(plan, ag, Wg, bg, relu=True, precision=prec, form="resample")
     o2 = dl.lsc_fwd(plan, ag, Wg, bg, relu=True, precision=prec, form="folded")
-    assert rel(o2, o1.double().cpu().numpy()) <= TOL[prec]
+    check("folded vs resample", o2, o1, prec)
 
 
 def test_lsc_empty_batch_zeroes_weight_grads():
@@ -367,7 +375,7 @@ def test_signal2sh_from_raw_fuses_b0_normalisation(prec, c2_acq):
     raw = raw.astype(np.float32).astype(np.float64)
     c = dl.signal2sh_fwd_raw(plan, cuda(raw), precision=prec)
     ref = osh.signal2sh(oplan, osh.normalize_b0(raw, acq.bvals, oplan))
-    assert rel(c, ref) <= TOL[prec]
+    check("c", c, ref, prec)
 
 
 def test_relative_mse():
@@ -378,7 +386,7 @@ def test_relative_mse():
     l_ref, g_ref = ostack.relative_mse(p.astype(np.float32).astype(np.float64), t.astype(np.float32).astype(np.float64),
                                        1e-3)
     assert abs(loss.item() - l_ref) / l_ref < 1e-5
-    assert rel(dp, g_ref) < 1e-5
+    check("dp", dp.reshape(-1, 1), g_ref.reshape(-1, 1), "fp32")
 
 
 def test_lsc_bf16_activation_storage_small_batches():
@@ -396,9 +404,10 @@ def test_lsc_bf16_activation_storage_small_batches():
         a64 = a_h.double().cpu().numpy()
         out = dl.lsc_fwd(plan, a_h, Wg, bg, precision="bf16", form="folded")
         out_ref, z = olsc.lsc_forward(oplan, a64, W, b, False)
-        assert rel(out, out_ref) <= TOL["bf16"]
+        check("out", out, out_ref, "bf16")
         da = cuda(np.random.default_rng(V).standard_normal((V, O, plan.K_out)))
         none, dW, db = dl.lsc_bwd(plan, a_h, Wg, da, need_input_grad=False, precision="bf16", form="folded")
         assert none is None
         _, dW_ref, db_ref = olsc.lsc_backward(oplan, a64, W, z, da.double().cpu().numpy(), False)
-        assert rel(dW, dW_ref) <= TOL["bf16"] and rel(db, db_ref) <= TOL["bf16"]
+        check("dW", dW, dW_ref, "bf16", kind="sum")
+        check("db", db, db_ref, "bf16", kind="sum")

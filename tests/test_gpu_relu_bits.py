@@ -14,15 +14,11 @@ import datagen as dg
 import paper_1808_01517_amd as dl
 from oracle import lsc as olsc
 
+from parity_util import check, fmt
+
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": 1e-5, "bf16": 2e-2}
 DEV = "cuda:0"
-
-
-def rel(out, ref):
-    out = out.detach().double().cpu().numpy()
-    return float(np.linalg.norm(out - ref) / max(np.linalg.norm(ref), 1e-300))
 
 
 def cuda(a):
@@ -69,7 +65,7 @@ def test_forward_writes_relu_bits(prec, store, V):
     assert np.array_equal(got, want), f"{int((got != want).sum())} words differ"
     assert 0 < (out > 0).float().mean().item() < 1
     out_ref, _ = olsc.lsc_forward(oplan, a.astype(np.float32).astype(np.float64), W, b, True)
-    assert rel(out.float(), out_ref) <= TOL[prec]
+    check("out", out.float(), out_ref, prec)
 
 
 @pytest.mark.parametrize("O", [3, 64])
@@ -100,10 +96,11 @@ def test_backward_with_relu_bits_matches_activation_mask(prec, store, O):
     a64 = a1.double().cpu().numpy()
     _, z = olsc.lsc_forward(oplan, a64, W2, b2, False)
     da_ref, dW_ref, db_ref = olsc.lsc_backward(oplan, a64, W2, z, da.double().cpu().numpy(), False)
-    errs = {"da_in": rel(g_b.float(), da_ref * (a64 > 0)), "dW": rel(dW_b, dW_ref), "db": rel(db_b, db_ref)}
-    print(f"[parity] relu bits bwd {prec} store={store} O={O}: "
-          + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
-    assert all(v <= TOL[prec] for v in errs.values()), errs
+    errs = {}
+    check("da_in", g_b.float(), da_ref * (a64 > 0), prec, errs)
+    check("dW", dW_b, dW_ref, prec, errs, kind="sum")
+    check("db", db_b, db_ref, prec, errs, kind="sum")
+    print(f"[parity] relu bits bwd {prec} store={store} O={O}: " + fmt(errs), flush=True)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
@@ -132,7 +129,7 @@ def test_relu_bits_on_short_rows(prec):
     a64 = a1.double().cpu().numpy()
     _, z = olsc.lsc_forward(oplan, a64, W2, b2, False)
     da_ref, _, _ = olsc.lsc_backward(oplan, a64, W2, z, da.double().cpu().numpy(), False)
-    assert rel(g_b, da_ref * (a64 > 0)) <= TOL[prec]
+    check("da_in", g_b, da_ref * (a64 > 0), prec)
 
 
 def test_relu_bits_rejects_unsupported():

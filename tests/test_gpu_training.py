@@ -14,14 +14,10 @@ from oracle import lsc as olsc
 from oracle import sh as osh
 from oracle import stack as ostack
 
+from parity_util import check, rel
+
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
-
-
-def rel(a, b):
-    a = a.detach().double().cpu().numpy() if isinstance(a, torch.Tensor) else np.asarray(a, np.float64)
-    b = b.detach().double().cpu().numpy() if isinstance(b, torch.Tensor) else np.asarray(b, np.float64)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def cu(a):
@@ -54,14 +50,14 @@ def test_modules_autograd_match_oracle():
                        osh.SHPlan(g, np.full(30, 1000.0), 4, 0.0))
     ref, cache = net.forward(xv)
     got = out.detach().permute(0, 2, 3, 4, 1).reshape(-1, 30)
-    assert rel(got, ref) <= 1e-5
+    check("out", got, ref, "fp32")
     up = rng.standard_normal(out.shape)
     out.backward(cu(up))
     upv = up.transpose(0, 2, 3, 4, 1).reshape(-1, 30)
     dx, dWs, dbs = net.backward(cache, upv)
-    assert rel(xt.grad.permute(0, 2, 3, 4, 1).reshape(-1, 30), dx) <= 1e-5
-    assert rel(lsc.sconv.weight.grad.reshape(1, 1, 6), dWs[0]) <= 1e-5
-    assert rel(lsc.sconv.bias.grad, dbs[0]) <= 1e-5
+    check("dx", xt.grad.permute(0, 2, 3, 4, 1).reshape(-1, 30), dx, "fp32")
+    check("dW", lsc.sconv.weight.grad.reshape(1, 1, 6), dWs[0], "fp32", kind="sum")
+    check("db", lsc.sconv.bias.grad, dbs[0], "fp32", kind="sum")
 
 
 def test_update_gradients_matches_fresh_plan():
@@ -74,7 +70,7 @@ def test_update_gradients_matches_fresh_plan():
     plan.update_gradients(dacq.bvecs)
     c_new = dl.signal2sh_fwd(plan, x)
     ref = osh.signal2sh(osh.SHPlan(dacq.bvecs, dacq.bvals, 8, 0.006), x.double().cpu().numpy())
-    assert rel(c_new, ref) <= 1e-5
+    check("c", c_new, ref, "fp32")
     assert rel(c_old, ref) > 1e-4   # the tables really changed
 
 
@@ -101,10 +97,10 @@ def test_c4_gradients_vs_oracle_and_finite_differences(form):
     xd, cd = f32(x), f32(clean)
     l_ref, _, dx_ref, dW_ref, db_ref = onet.loss_and_grads(xd, cd)
     assert abs(float(loss) - l_ref) / l_ref <= 1e-5
-    assert rel(dx, dx_ref) <= 1e-5
+    check("dx", dx, dx_ref, "fp32")
     for k in range(4):
-        assert rel(net.dW[k], dW_ref[k]) <= 1e-5, k
-        assert rel(net.db[k], db_ref[k]) <= 1e-5, k
+        check(f"dW{k}", net.dW[k], dW_ref[k], "fp32", kind="sum")
+        check(f"db{k}", net.db[k], db_ref[k], "fp32", kind="sum")
     # FP64 central differences of the oracle's loss at sampled coordinates
     rng = np.random.default_rng(11)
     h = 1e-6
@@ -198,15 +194,17 @@ def test_learned_network_gradients_vs_oracle(prec, half):
     xhat = net.xhat[:128].double().cpu().numpy()
     _, dxh = ostack.mse(xhat, tgt)
     _, dWs, dbs = onet.backward((cache[0], zs), dxh)
-    tol = 1e-5 if prec == "fp32" else 2e-2
     for k in range(3):
-        assert rel(net.dW[k], dWs[k]) <= tol, (k, rel(net.dW[k], dWs[k]))
-        assert rel(net.db[k], dbs[k]) <= tol
+        check(f"dW{k}", net.dW[k], dWs[k], prec, kind="sum")
+        check(f"db{k}", net.db[k], dbs[k], prec, kind="sum")
 
 
 def test_learned_predictor_beats_plain_fit():
-    res, S, net = apps.run_learned(train_voxels=1 << 17, eval_voxels=1 << 14, epochs=6, lr=2e-3, batch=4096)
+    """Trained on 131 072 voxels (a short run), scored on the 262 144
+    held-out voxels of the learned-form workload."""
+    res, S, net = apps.run_learned(train_voxels=1 << 17, eval_voxels=1 << 18, epochs=6, lr=2e-3, batch=4096)
     print(res)
+    assert res["eval_voxels"] == 1 << 18
     assert res["nrmse_net_vs_clean"] < res["nrmse_fit_vs_clean"]
     # the plain fit computed by the library matches the oracle's fit on a sample
     w = dg.C5
@@ -216,4 +214,4 @@ def test_learned_predictor_beats_plain_fit():
     sub, acq = S["sub"], S["acq"]
     ref = osh.sh2signal(osh.SHPlan(acq.bvecs, acq.bvals, 4, 0.0),
                         osh.signal2sh(osh.SHPlan(sub.bvecs, sub.bvals, 4, w.lb_lambda), xs))
-    assert rel(got, ref) <= 1e-5
+    check("plain fit", got, ref, "fp32")
