@@ -154,6 +154,22 @@ size_t dlm_sh2signal_mse_workspace_bytes(const dlm_sh_plan *plan, int64_t V);
 dlm_status dlm_sh2signal_mse_fwd_bwd(const dlm_sh_plan *plan, const float *c, const float *target, int64_t V,
                                      float *loss, float *dc, float *xhat, void *ws, size_t ws_bytes,
                                      dlm_precision prec, void *stream);
+/* dlm_sh2signal_mse_fwd_bwd without a workspace, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid allocation).  The partial sums live in a static
+ * device array of dlm_sh2signal_mse_static_scratch_bytes() bytes (4 MiB),
+ * one per device, held until the process ends; calls whose
+ * dlm_sh2signal_mse_workspace_bytes(plan, V) exceeds it return
+ * DLM_EWORKSPACE (about 5.59 M voxels of a three-shell table fit).  The
+ * call allocates nothing (with timing off, the default): its first call on
+ * a device only looks up that device's array address.  Every call on one
+ * device shares the array and leaves its contents behind; nothing in it
+ * needs clearing, but calls that overlap on one device (other streams,
+ * unordered host threads) race.  Results are those of
+ * dlm_sh2signal_mse_fwd_bwd, bit for bit. */
+size_t dlm_sh2signal_mse_static_scratch_bytes(void);
+dlm_status dlm_sh2signal_mse_fwd_bwd_noalloc(const dlm_sh_plan *plan, const float *c, const float *target, int64_t V,
+                                             float *loss, float *dc, float *xhat, dlm_precision prec, void *stream);
 
 /* Signal2SH straight from raw acquisitions, with the b=0 normalisation the
  * layer requires of its input (Sec. 2.2) fused into the load:

@@ -59,6 +59,8 @@ SIGNATURES = {
     "dlm_sh2signal_mse_supported": (_int, [_p]),
     "dlm_sh2signal_mse_workspace_bytes": (C.c_size_t, [_p, _i64]),
     "dlm_sh2signal_mse_fwd_bwd": (_st, [_p, _p, _p, _i64, _p, _p, _p, _p, C.c_size_t, _int, _p]),
+    "dlm_sh2signal_mse_static_scratch_bytes": (C.c_size_t, []),
+    "dlm_sh2signal_mse_fwd_bwd_noalloc": (_st, [_p, _p, _p, _i64, _p, _p, _p, _int, _p]),
     "dlm_timing_enable": (_st, [_int]),
     "dlm_timing_reset": (_st, []),
     "dlm_timing_count": (_int, []),
