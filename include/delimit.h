@@ -347,6 +347,21 @@ int dlm_timing_count(void);
 dlm_status dlm_timing_entry(int i, char *tag, size_t tag_len, double *total_ms, int64_t *launches,
                             double *alg_bytes, double *alg_flops);
 
+/* Reference kernels for the roofline, measured on the same GPU as the
+ * layers (the rates a streaming kernel and the matrix cores deliver there,
+ * next to the spec-sheet peaks).
+ * dlm_peak_copy: device-to-device copy of `bytes` (a multiple of 4; both
+ * buffers 16-byte aligned, not overlapping); it moves 2 * bytes through
+ * HBM.  dlm_peak_mfma: `blocks` workgroups of four waves each run `iters`
+ * rounds of independent MFMAs (sixteen v_mfma_f32_16x16x4_f32 for DLM_FP32,
+ * eight v_mfma_f32_32x32x16_bf16 for DLM_BF16) and write one float per lane to
+ * out (device, dlm_peak_mfma_out_floats(blocks) floats); the work done is
+ * dlm_peak_mfma_flops(prec, blocks, iters) flops. */
+dlm_status dlm_peak_copy(const void *src, void *dst, size_t bytes, void *stream);
+size_t dlm_peak_mfma_out_floats(int blocks);
+double dlm_peak_mfma_flops(dlm_precision prec, int blocks, int iters);
+dlm_status dlm_peak_mfma(dlm_precision prec, int blocks, int iters, float *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

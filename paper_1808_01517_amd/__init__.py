@@ -23,7 +23,7 @@ __all__ = [
     "lsc_fwd", "lsc_bwd", "lsc_workspace_bytes", "mse_fwd_bwd", "adam_step", "Workspace", "DelimitError",
     "sh_basis", "sh_fit_matrix", "lsc_kernel_points", "timing_enable", "timing_reset", "timing_report",
     "form_code", "DEFAULT_FORM", "signal2sh_fwd_raw", "relmse_fwd_bwd", "sh2signal_mse_supported",
-    "sh2signal_mse_fwd_bwd",
+    "sh2signal_mse_fwd_bwd", "peak_copy", "peak_mfma",
 ]
 
 
@@ -455,6 +455,26 @@ def relmse_fwd_bwd(pred: torch.Tensor, target: torch.Tensor, eps: float = 1e-3, 
     check(lib().dlm_relmse_fwd_bwd(_ptr(pred), _ptr(target), n, float(eps), _ptr(loss), _ptr(dpred), _ptr(ws),
                                    ws.numel(), _stream(pred)))
     return loss, dpred
+
+
+def peak_copy(src: torch.Tensor, dst: torch.Tensor) -> None:
+    """The reference copy kernel: dst <- src (device tensors of equal byte size)."""
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("peak_copy needs contiguous device tensors")
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != n:
+        raise ValueError("peak_copy buffers differ in size")
+    check(lib().dlm_peak_copy(_ptr(src), _ptr(dst), n, _stream(src)))
+
+
+def peak_mfma(precision, blocks: int, iters: int, out: torch.Tensor) -> float:
+    """Run the reference MFMA loop; returns the flops it does.  out: float32
+    device tensor of at least lib().dlm_peak_mfma_out_floats(blocks) entries."""
+    if out.dtype != torch.float32 or not out.is_cuda or out.numel() < lib().dlm_peak_mfma_out_floats(blocks):
+        raise ValueError("out must be a float32 device tensor of blocks * 256 entries")
+    prec = precision_code(precision)
+    check(lib().dlm_peak_mfma(prec, int(blocks), int(iters), _ptr(out), _stream(out)))
+    return float(lib().dlm_peak_mfma_flops(prec, int(blocks), int(iters)))
 
 
 def timing_enable(on: bool = True) -> None:

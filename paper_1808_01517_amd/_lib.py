@@ -61,6 +61,10 @@ SIGNATURES = {
     "dlm_sh2signal_mse_fwd_bwd": (_st, [_p, _p, _p, _i64, _p, _p, _p, _p, C.c_size_t, _int, _p]),
     "dlm_sh2signal_mse_static_scratch_bytes": (C.c_size_t, []),
     "dlm_sh2signal_mse_fwd_bwd_noalloc": (_st, [_p, _p, _p, _i64, _p, _p, _p, _int, _p]),
+    "dlm_peak_copy": (_st, [_p, _p, C.c_size_t, _p]),
+    "dlm_peak_mfma_out_floats": (C.c_size_t, [_int]),
+    "dlm_peak_mfma_flops": (_dbl, [_int, _int, _int]),
+    "dlm_peak_mfma": (_st, [_int, _int, _int, _p, _p]),
     "dlm_timing_enable": (_st, [_int]),
     "dlm_timing_reset": (_st, []),
     "dlm_timing_count": (_int, []),

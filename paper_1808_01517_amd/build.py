@@ -21,7 +21,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{os
 # Device code: gfx950 only; no packed-FP32 instructions.
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-fno-gpu-flush-denormals-to-zero"]
-SOURCES = ["kernels.hip", "stream.hip", "shell.hip", "noalloc.hip", "capi.cpp", "host_tables.cpp", "timing.cpp"]
+SOURCES = ["kernels.hip", "stream.hip", "shell.hip", "noalloc.hip", "peaks.hip", "capi.cpp", "host_tables.cpp", "timing.cpp"]
 
 
 def _compile(src: str, verbose: bool) -> str:
