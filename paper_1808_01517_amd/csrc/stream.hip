@@ -45,6 +45,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "gemm_common.h"
 #include "internal.h"
@@ -53,6 +54,10 @@ namespace dlm {
 namespace streaming {
 
 constexpr int SBK = 32;  // reduction entries per stage (one MFMA deep)
+
+#ifndef DLM_ASTAT
+#define DLM_ASTAT 1  // the short-reduction kernel below (0: tiled core only)
+#endif
 
 #define DLM_LDS(p) ((__attribute__((address_space(3))) void *)(p))
 
@@ -728,6 +733,8 @@ template <bool BIAS, bool MASK, int BM = 0>
 struct CRowSide {
   static constexpr bool kSide = BIAS || MASK;
   static constexpr bool kPair = false;
+  static constexpr bool kBias = BIAS, kMask = MASK, kHalf = false;
+  static constexpr int kBits = BM;
   float *C;
   int64_t ldc;
   int relu;
@@ -777,6 +784,8 @@ template <bool BIAS, bool MASK, int BM = 0>
 struct CRowSideH {
   static constexpr bool kSide = BIAS || MASK;
   static constexpr bool kPair = true;
+  static constexpr bool kBias = BIAS, kMask = MASK, kHalf = true;
+  static constexpr int kBits = BM;
   uint16_t *C;
   int64_t ldc;
   int relu;
@@ -884,6 +893,448 @@ struct CRowSideH {
   }
 };
 
+// --------------------------------------------- short-reduction kernel
+// C[M][N] = A[M][K] B[N][K]^T for 128 < K <= 160 and N <= 1440: the folded
+// forward of a layer with three input channels and the input gradient of a
+// layer with three output channels (K = 135, N = 1440 in the three-shell
+// stack).  With five k-slices per tile, a block of the tiled core above
+// spends most of its life waiting for the loads of its first slices.  Here
+// a block keeps its rows of A in registers, loaded once, and sweeps every
+// column tile of the table, which streams through an LDS ring by DMA (the
+// table stays in L2).  The stores of one tile are in flight while the next
+// tiles are loaded and multiplied.
+//
+// Waits count vector-memory operations in issue order: the DMA of tile t
+// is waited for with s_waitcnt vmcnt(n), n = a lower bound of the
+// operations the wave issued after it (the stores of the tiles in between,
+// the DMA of later tiles).  The block holding the last rows skips the
+// stores of rows beyond M, so there the store count is taken as zero.
+//
+// Side data stay in LDS for the block's whole life: the bias of every
+// column (forward), the ReLU bit words of the block's rows (the input
+// gradient's mask), or the bit words the forward produces for the block's
+// rows, which go to memory once, as one contiguous run, when the block ends.
+// Per element the epilogue is the tiled core's (bias, ReLU, mask, RNE
+// rounding, bits of the stored value) with the ReLU chosen at compile time;
+// the accumulation order is also the tiled core's (k-slices in order; FP32:
+// within a slice, k groups of 16, then the four MFMAs of a group), so with
+// one accumulator set the results are bitwise the same.
+namespace astat {
+
+#ifndef DLM_ASTAT_TM
+#define DLM_ASTAT_TM 2
+#endif
+#ifndef DLM_ASTAT_BN_BF16
+#define DLM_ASTAT_BN_BF16 32
+#endif
+#ifndef DLM_ASTAT_BN_F32
+#define DLM_ASTAT_BN_F32 32
+#endif
+#ifndef DLM_ASTAT_NACC
+#define DLM_ASTAT_NACC 1
+#endif
+#ifndef DLM_ASTAT_D_BF16
+#define DLM_ASTAT_D_BF16 3
+#endif
+#ifndef DLM_ASTAT_D_F32
+#define DLM_ASTAT_D_F32 1
+#endif
+
+constexpr int TM = DLM_ASTAT_TM;  // 16-row groups per wave
+constexpr int BM = 64 * TM;       // rows per block: four waves
+constexpr int KS = 5;             // 32-k slices (128 < K <= 160)
+constexpr int kMaxN = 1440;       // columns whose side data fit in LDS
+
+// BF16: lane (q16, g4) holds A[row][32 s + 8 g4 .. + 7] rounded to bfloat16;
+// FP32: A[row][16 g + 4 g4 .. + 3], g < 2 KS (row = 16 i + q16 of the wave).
+template <bool F32>
+struct AFrag {
+  bf16x8 v[TM][KS];
+};
+template <>
+struct AFrag<true> {
+  floatx4 v[TM][2 * KS];
+};
+
+// NV consecutive values of a row from k0 on, zeros at and beyond K.
+template <int NV>
+__device__ __forceinline__ void load_run(const float *row, int k0, int K, float (&out)[NV]) {
+  if (k0 + NV <= K) {
+#pragma unroll
+    for (int q = 0; q < NV / 4; ++q) {
+      const floatx4 t = ld4(row + k0 + 4 * q);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) out[4 * q + e] = t[e];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < NV; ++e) out[e] = k0 + e < K ? row[k0 + e] : 0.0f;
+  }
+}
+
+template <bool F32>
+__device__ __forceinline__ void load_a(const float *A, int64_t lda, int64_t M, int K, int64_t r0, int q16, int g4,
+                                       AFrag<F32> &a) {
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    int64_t r = r0 + i * 16 + q16;
+    if (r >= M) r = M - 1;  // rows beyond M read a valid row and are never stored
+    const float *row = A + r * lda;
+    if constexpr (F32) {
+#pragma unroll
+      for (int g = 0; g < 2 * KS; ++g) {
+        float t[4];
+        load_run<4>(row, 16 * g + 4 * g4, K, t);
+        a.v[i][g] = floatx4{t[0], t[1], t[2], t[3]};
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        float t[8];
+        load_run<8>(row, 32 * s + 8 * g4, K, t);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a.v[i][s][e] = (__bf16)t[e];
+      }
+    }
+  }
+}
+
+template <class CS>
+constexpr int bias_bytes() {
+  return CS::kBias ? kMaxN * 4 : 0;
+}
+template <class CS>
+constexpr int side_bytes() {
+  constexpr int b = bias_bytes<CS>() + ((CS::kMask || CS::kBits == 1) ? BM * (kMaxN / 16) * 2 : 0);
+  return b > 0 ? b : 16;
+}
+
+// The 16-bit ReLU word of one row's 16-column tile: each of the row's four
+// lanes (q16, g4) holds the nibble of its four columns; two row swaps OR
+// them together in every lane.
+__device__ __forceinline__ unsigned bits_word(unsigned nib, int g4) {
+  unsigned w = nib << (4 * g4);
+  const auto s16 = __builtin_amdgcn_permlane16_swap(w, w, false, false);
+  w = s16[0] | s16[1];
+  const auto s32 = __builtin_amdgcn_permlane32_swap(w, w, false, false);
+  return s32[0] | s32[1];
+}
+
+// Two adjacent 16-column tiles of one row in bfloat16 (lane g4 holds
+// columns 4 g4 .. 4 g4 + 3 of both, two packed words each): a row swap
+// hands each lane 8 contiguous columns, stored with one 16-byte store.
+__device__ __forceinline__ void store_pair_bf16(uint16_t *C, int64_t ldc, int64_t r, int nt, int g4,
+                                                const uint32_t (&w0)[2], const uint32_t (&w1)[2]) {
+  const bool odd = g4 & 1;
+  uint32_t out[4];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const uint32_t mine = odd ? w0[q] : w1[q];  // the half the partner stores
+    const auto x = __builtin_amdgcn_permlane16_swap(mine, mine, false, false);
+    const uint32_t theirs = x[0] ^ x[1] ^ mine;  // one result is this lane's own value
+    if (odd) {
+      out[q] = theirs;
+      out[2 + q] = w1[q];
+    } else {
+      out[q] = w0[q];
+      out[2 + q] = theirs;
+    }
+  }
+  const int col = odd ? nt + 16 + 4 * (g4 - 1) : nt + 4 * g4;
+  __builtin_memcpy(C + r * ldc + col, out, 16);
+}
+
+template <bool F32, int BN, int D, int NACC, bool RELU, class BO, class CS>
+__global__ __launch_bounds__(256) void astat_kernel(const float *A, int64_t lda, int64_t M, int K, BO bo, CS cs,
+                                                    int N) {
+  constexpr int TN = BN / 16, NS = D + 1;
+  constexpr bool kHalf = CS::kHalf, kMaskIn = CS::kMask, kBitsOut = CS::kBits == 1;
+  static_assert(!CS::kMask || CS::kBits == 2, "masks from ReLU bits only");
+  constexpr int SLAB = BO::template bytes<BN>();  // one 32-k slice of a column tile
+  constexpr int TILE = KS * SLAB;
+  constexpr int NSL = BO::template slots<BN>();
+  static_assert(BO::kUnit == 16 && NSL % 64 == 0, "whole 16-byte DMA instructions per slice");
+  constexpr int NI = NSL / 64;        // DMA instructions per slice
+  constexpr int NIT = KS * NI;        // per tile, dealt round-robin to the four waves
+  constexpr int KW = (NIT + 3) / 4;   // per wave per tile, at most
+  constexpr int IW = NIT / 4;         // and at least
+  constexpr int KB = BO::template bytes<1>() / SBK;  // bytes per table entry
+  // stores per wave per tile, at least: one per pair of bfloat16 tiles (and
+  // per odd tile), or one per float32 tile
+  constexpr int SW = TM * (kHalf ? (TN + 1) / 2 : TN);
+  static_assert(D >= 1 && D <= 3 && D * SW + (D - 1) * IW < 64, "vmcnt range");
+  __shared__ __attribute__((aligned(16))) char lds[NS * TILE + side_bytes<CS>()];
+  float *sbias = reinterpret_cast<float *>(lds + NS * TILE);
+  uint16_t *sbits = reinterpret_cast<uint16_t *>(lds + NS * TILE + bias_bytes<CS>());
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q16 = lane & 15, g4 = lane >> 4;
+  const int64_t m0 = (int64_t)blockIdx.x * BM;
+  const int64_t r0 = m0 + wave * 16 * TM;
+  const int NT = N / BN;
+  const int wpr = N / 16;  // ReLU-bit words per row
+  const bool full = m0 + BM <= M;
+
+  // The wave's DMA instructions of a tile (q = wave + 4k: slice q / NI,
+  // instruction q % NI of it): per-lane byte offsets from the tile's first
+  // table row, and LDS offsets in the slot (the same for every tile: N is a
+  // multiple of BN, so no row is clamped).
+  uint32_t voff[KW];
+  int loff[KW];
+  const int nq = (NIT - wave + 3) / 4;
+#pragma unroll
+  for (int k = 0; k < KW; ++k) {
+    const int q = wave + 4 * k, sl = q / NI, ins = q - sl * NI;
+    voff[k] = q < NIT ? bo.template lane_off<BN>(ins * 64 + lane, 0) + uint32_t(sl * SBK * KB) : 0u;
+    loff[k] = sl * SLAB + ins * 64 * 16;
+  }
+  const char *gtab = bo.base(0, 0);
+  const int64_t tstride = bo.base(BN, 0) - gtab;  // bytes between column tiles
+  auto issue = [&](int t) {
+    const char *src = gtab + (int64_t)t * tstride;
+    char *dst = lds + (t % NS) * TILE;
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+      if (k < nq) {
+        uint32_t o = voff[k];
+        asm volatile("" : "+v"(o));
+        dma_to_lds<16>(src + o, dst + loff[k]);
+      }
+    }
+  };
+
+  // prologue: A into registers, the first tiles and the side data into LDS
+  AFrag<F32> a;
+  load_a<F32>(A, lda, M, K, r0, q16, g4, a);
+#pragma unroll
+  for (int t = 0; t < D; ++t)
+    if (t < NT) issue(t);
+  if constexpr (CS::kBias)
+    for (int c = tid; c < N; c += 256) sbias[c] = cs.bias_n[c];
+  if constexpr (kMaskIn) {
+    for (int c = tid; c < BM * wpr; c += 256) {
+      const int rr = c / wpr;
+      int64_t r = m0 + rr;
+      if (r >= M) r = M - 1;
+      sbits[c] = cs.mbits[r * wpr + (c - rr * wpr)];
+    }
+  }
+  wait_barrier<0>();
+
+  for (int t = 0; t < NT; ++t) {
+    if (t >= D) {
+      // after the DMA of tile t this wave issued: the stores of tiles
+      // t-D .. t-1 and the DMA of tiles t+1 .. t+D-1 (those that exist)
+      const int later = min(D - 1, NT - 1 - t);
+      if constexpr (D == 1) {
+        if (full) wait_barrier<SW>();
+        else wait_barrier<0>();
+      } else if constexpr (D == 2) {
+        if (full) {
+          if (later) wait_barrier<2 * SW + IW>();
+          else wait_barrier<2 * SW>();
+        } else {
+          if (later) wait_barrier<IW>();
+          else wait_barrier<0>();
+        }
+      } else {
+        if (full) {
+          if (later == 2) wait_barrier<3 * SW + 2 * IW>();
+          else if (later == 1) wait_barrier<3 * SW + IW>();
+          else wait_barrier<3 * SW>();
+        } else {
+          if (later == 2) wait_barrier<2 * IW>();
+          else if (later == 1) wait_barrier<IW>();
+          else wait_barrier<0>();
+        }
+      }
+    } else if (t > 0) {
+      // every wave is done reading the slot refilled next (tiles t < D
+      // arrived before the prologue's barrier)
+      asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    }
+    if (t + D < NT) issue(t + D);
+
+    const char *tile = lds + (t % NS) * TILE;
+    floatx4 acc[NACC][TM][TN];
+#pragma unroll
+    for (int u = 0; u < NACC; ++u)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[u][i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int sl = 0; sl < KS; ++sl) {
+      const char *sb = tile + sl * SLAB;
+      if constexpr (F32) {
+        const int nh = K - SBK * sl > 16 ? 2 : 1;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (h < nh) {
+            floatx4 b[TN];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) b[j] = bo.template frag4<BN>(sb, j, q16, g4, h);
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+              for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                  acc[jj % NACC][i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[j][jj], a.v[i][2 * sl + h][jj],
+                                                                              acc[jj % NACC][i][j], 0, 0, 0);
+          }
+        }
+      } else {
+        bf16x8 b[TN];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) b[j] = bo.template frag<BN>(sb, j, q16, g4);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[0][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j], a.v[i][sl], acc[0][i][j], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int u = 1; u < NACC; ++u)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[0][i][j] += acc[u][i][j];
+
+    // epilogue: bias, ReLU, mask, rounding, bits; then the stores
+    const int n0 = t * BN;
+    floatx4 cbv[TN];
+    if constexpr (CS::kBias) {
+#pragma unroll
+      for (int j = 0; j < TN; ++j) cbv[j] = *reinterpret_cast<const floatx4 *>(sbias + n0 + 16 * j + 4 * g4);
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int rr = wave * 16 * TM + i * 16 + q16;
+      const int64_t r = m0 + rr;
+      floatx4 v[TN];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        v[j] = acc[0][i][j];
+        unsigned mnib = 15u;
+        if constexpr (kMaskIn) mnib = (unsigned)sbits[rr * wpr + n0 / 16 + j] >> (4 * g4);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if constexpr (CS::kBias) v[j][q] += cbv[j][q];
+          if constexpr (RELU) v[j][q] = fmaxf(v[j][q], 0.0f);
+          if constexpr (kMaskIn) v[j][q] = (mnib >> q) & 1u ? v[j][q] : 0.0f;
+        }
+      }
+      if constexpr (kHalf) {
+        uint32_t h2[TN][2];
+        unsigned nib[TN];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          nib[j] = 0;
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const uint16_t lo = to_bf16_bits(v[j][2 * q]), hi = to_bf16_bits(v[j][2 * q + 1]);
+            h2[j][q] = (uint32_t)lo | ((uint32_t)hi << 16);
+            if constexpr (kBitsOut)  // the stored (rounded) value is > 0
+              nib[j] |= ((__builtin_bit_cast(float, (uint32_t)lo << 16) > 0.0f ? 1u : 0u) |
+                         (__builtin_bit_cast(float, (uint32_t)hi << 16) > 0.0f ? 2u : 0u))
+                        << (2 * q);
+          }
+        }
+        if constexpr (kBitsOut) {
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            const unsigned w = bits_word(nib[j], g4);
+            if (g4 == 0) sbits[rr * wpr + n0 / 16 + j] = (uint16_t)w;
+          }
+        }
+        if (r >= M) continue;
+#pragma unroll
+        for (int jp = 0; jp < TN / 2; ++jp)
+          store_pair_bf16(cs.C, cs.ldc, r, n0 + 32 * jp, g4, h2[2 * jp], h2[2 * jp + 1]);
+        if constexpr (TN % 2 != 0) __builtin_memcpy(cs.C + r * cs.ldc + n0 + 16 * (TN - 1) + 4 * g4, h2[TN - 1], 8);
+      } else {
+        if constexpr (kBitsOut) {
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            unsigned nib = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) nib |= (v[j][q] > 0.0f ? 1u : 0u) << q;
+            const unsigned w = bits_word(nib, g4);
+            if (g4 == 0) sbits[rr * wpr + n0 / 16 + j] = (uint16_t)w;
+          }
+        }
+        if (r >= M) continue;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) __builtin_memcpy(cs.C + r * cs.ldc + n0 + 16 * j + 4 * g4, &v[j], 16);
+      }
+    }
+  }
+
+  if constexpr (kBitsOut) {
+    // the block's bit words, rows m0 .. m0 + BM - 1 (those below M): one
+    // contiguous run of memory
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    const int64_t rows = min((int64_t)BM, M - m0);
+    const int64_t nw = rows * wpr;
+    uint16_t *dst = cs.obits + m0 * wpr;
+    if (((reinterpret_cast<uintptr_t>(dst)) & 15) == 0) {
+      const int64_t n16 = nw / 8;
+      for (int64_t c = tid; c < n16; c += 256)
+        __builtin_memcpy(dst + 8 * c, reinterpret_cast<const uint4 *>(sbits) + c, 16);
+      for (int64_t c = 8 * n16 + tid; c < nw; c += 256) dst[c] = sbits[c];
+    } else {
+      for (int64_t c = tid; c < nw; c += 256) dst[c] = sbits[c];
+    }
+  }
+}
+
+// Which output policies the kernel takes: bias or none, or the ReLU mask
+// from bit words (an activation mask would be as large as the output).
+template <class CS>
+constexpr bool takes() {
+  return !CS::kMask || CS::kBits == 2;
+}
+
+// DLM_TILED_ONLY=1 in the environment sends these GEMMs to the tiled core
+// instead (the same results bit for bit; read at every call, for tests).
+inline bool tiled_only() {
+  const char *e = std::getenv("DLM_TILED_ONLY");
+  return e && e[0] == '1';
+}
+
+template <bool F32>
+bool ok(const TableGemm &t) {
+  constexpr int BN = F32 ? DLM_ASTAT_BN_F32 : DLM_ASTAT_BN_BF16;
+  return DLM_ASTAT != 0 && !tiled_only() && t.A != nullptr && t.Ah == nullptr && t.K > SBK * (KS - 1) && t.K <= SBK * KS &&
+         t.N % BN == 0 && t.N <= kMaxN && t.N % 16 == 0 && t.M > 0 && (t.M + BM - 1) / BM <= 0x7fffffff;
+}
+
+template <bool F32, class BO, class CS>
+int run(const TableGemm &t, BO bo, CS cs, hipStream_t st) {
+  constexpr int BN = F32 ? DLM_ASTAT_BN_F32 : DLM_ASTAT_BN_BF16;
+  constexpr int D = F32 ? DLM_ASTAT_D_F32 : DLM_ASTAT_D_BF16;
+  constexpr int NACC = F32 ? DLM_ASTAT_NACC : 1;
+  const unsigned blocks = (unsigned)((t.M + BM - 1) / BM);
+  if constexpr (CS::kBias) {  // the forward: ReLU fused or not
+    if (t.relu)
+      hipLaunchKernelGGL((astat_kernel<F32, BN, D, NACC, true, BO, CS>), dim3(blocks), dim3(256), 0, st, t.A, t.lda,
+                         t.M, t.K, bo, cs, t.N);
+    else
+      hipLaunchKernelGGL((astat_kernel<F32, BN, D, NACC, false, BO, CS>), dim3(blocks), dim3(256), 0, st, t.A, t.lda,
+                         t.M, t.K, bo, cs, t.N);
+  } else {
+    if (t.relu) return -3;  // an input gradient never fuses a ReLU
+    hipLaunchKernelGGL((astat_kernel<F32, BN, D, NACC, false, BO, CS>), dim3(blocks), dim3(256), 0, st, t.A, t.lda,
+                       t.M, t.K, bo, cs, t.N);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace astat
+
 // BF16, N > 96 (N = 135/136, and 1440/2880 = 10/20 tiles exactly): one
 // configuration; for the K = 135 GEMMs it also amortises a block's fixed
 // cost (DMA offsets, first loads, epilogue) over 1.5x the output of 128 x 96
@@ -899,6 +1350,8 @@ using SCfgGrad = SCfg<128, 144, 4, 1, 2>;
 
 template <int OP, bool F32, class AO, class BO, class CS>
 int stream_table_c(AO ao, BO bo, CS cs, const TableGemm &t, hipStream_t st) {
+  if constexpr (astat::takes<CS>())
+    if (astat::ok<F32>(t)) return astat::run<F32>(t, bo, cs, st);
   if (t.N <= 96) return run_stream<OP, SCfgSmall, F32>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);
   if constexpr (F32)
     if (t.N > 144) return run_stream<OP, SCfgWideF32, F32>(ao, bo, cs, t.M, t.N, t.K, 1, 0, st);

@@ -111,6 +111,8 @@ def _lsc_case(C, O, L_in, L_out, ks, m_dirs, V, seed):
     (3, 32, 8, 8, (8, 8), 90, 203),
     (32, 3, 8, 8, (8, 8), 90, 203),
     (3, 5, 4, 8, (8, 8), 90, 131),
+    (5, 16, 6, 6, (8, 8), 90, 301),
+    (16, 5, 6, 6, (8, 8), 90, 301),
 ])
 @pytest.mark.parametrize("relu", [False, True])
 def test_lsc_forward_backward(prec, case, relu, form):

@@ -163,3 +163,40 @@ def test_relu_bits_rejects_unsupported():
     g0, dW0, db0 = dl.lsc_bwd(plan, empty, W3g, torch.zeros((0, 3, plan.K_out), device=DEV), relu_in=True,
                               form="folded", relu_bits=e_bits)
     assert g0.shape[0] == 0 and float(dW0.abs().max()) == 0.0 and float(db0.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("case", [(3, 32, 8, 1000 + 77), (5, 16, 6, 517)])
+@pytest.mark.parametrize("prec,store", [("fp32", torch.float32), ("bf16", torch.float32), ("bf16", torch.bfloat16)])
+def test_short_reduction_kernel_matches_tiled_core(case, prec, store, monkeypatch):
+    """The folded GEMMs with a short reduction (C * K_in or O * K_out in
+    129..160: the forward of a layer with few input channels, the input
+    gradient of a layer with few output channels) run on a kernel that keeps
+    its rows of A in registers; DLM_TILED_ONLY=1 sends them to the tiled
+    core.  Both accumulate in the same order: outputs, ReLU bits and input
+    gradients are bitwise equal, with a ragged last block of rows."""
+    C, O, L, V = case
+    oplan, plan = _plan(L=L)
+    W1, b1 = _weights(31, C, O, plan.T)
+    W2, _ = _weights(32, O, C, plan.T)
+    x = cuda(np.random.default_rng(12).standard_normal((V, C, plan.K_in)))
+    d = cuda(np.random.default_rng(13).standard_normal((V, C, plan.K_out)))
+    W1g, b1g, W2g = cuda(W1), cuda(b1), cuda(W2)
+
+    def run():
+        a1 = torch.empty((V, O, plan.K_out), dtype=store, device=DEV)
+        bits = dl.relu_bits_like(a1)
+        dl.lsc_fwd(plan, x, W1g, b1g, relu=True, out=a1, precision=prec, form="folded", relu_bits=bits)
+        g, _, _ = dl.lsc_bwd(plan, a1, W2g, d, relu_in=True, precision=prec, form="folded", relu_bits=bits,
+                             need_weight_grad=False, need_bias_grad=False)
+        torch.cuda.synchronize()
+        return a1, bits, g
+
+    monkeypatch.delenv("DLM_TILED_ONLY", raising=False)
+    fast = run()
+    monkeypatch.setenv("DLM_TILED_ONLY", "1")
+    tiled = run()
+    for name, u, w in zip(("a_out", "bits", "da_in"), fast, tiled):
+        assert torch.equal(u, w), name
+    monkeypatch.delenv("DLM_TILED_ONLY")
+    out_ref, _ = olsc.lsc_forward(oplan, x.double().cpu().numpy(), W1, b1, True)
+    check("a_out", fast[0].float(), out_ref, prec)
