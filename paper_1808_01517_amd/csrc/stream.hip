@@ -21,8 +21,11 @@
 //   4 KB zero buffer (spread over lanes, so no single cache line is hot).
 //   LDS thus holds the exact operands and fragment reads need no
 //   conditionals.  Rows beyond the matrix are clamped to valid rows (their
-//   outputs are never stored); the weight gradient's ones row is one of
-//   them, and its fragments are set to ones in registers.
+//   outputs are never stored).  The weight gradient's ones row (its bias
+//   term) is one of them: in FP32 the wave whose tiles hold it sums the
+//   other operand's fragments as they pass, and the epilogue stores those
+//   sums in place of the row's MFMA results; BF16 sets the row's fragments
+//   to ones in registers.
 // * Every LDS layout is swizzled so that fragment reads avoid bank
 //   conflicts while each DMA instruction still fills 64 consecutive slots
 //   (the hardware writes lane i of an instruction to base + i * size).
@@ -113,6 +116,7 @@ struct SKc {
   const float *p;
   int64_t ld, rows;
   static constexpr int kUnit = VEC ? 16 : 4;
+  static constexpr bool kOnes = false;
   template <int BR>
   static constexpr int bytes() { return BR * SBK * 4; }
   template <int BR>
@@ -160,25 +164,29 @@ struct SKc {
 };
 
 // Row-contiguous float32: element (r, k) at p[k * ld + r], valid for
-// r < rows, k < kend; row `ones` (if >= 0) reads as 1 (bind() locates it in
-// the block's tile).
-// LDS: [32][BR] floats (k-major); row r of k-line k is stored at
-// (r + 16 h(k)) mod BR with h(k) = bit 2 xor bit 3 of k, so the lanes of a
-// fragment read that differ in k land 16 banks apart.  VEC needs 16-byte
-// aligned k-lines and rows % 4 == 0.
-template <bool VEC>
+// r < rows, k < kend; with ONES, row `ones` (if >= 0) stands for a row of
+// ones (bind() locates it in the block's tile).  VEC needs 16-byte aligned k-lines and rows % 4 == 0.
+// LDS: a stage (32 k x BR rows) in windows of 16 rows of one k (64 bytes).
+// With k = 16 h + 4 q + j (h = bit 4, q = bits 2-3, j = bits 0-1) and
+// NG = BR / 16 row groups, window (k, rg) sits at window index
+// 4 ((4 h + j) NG + rg) + c(k), c(k) = 2 bit3(k) + (bit2(k) xor bit4(k)).
+// The four k of one fragment read (FP32: 16 h + 4 g4 + j over g4; BF16:
+// 8 g4 + e over g4) have four different c, so the 64 lanes of the read
+// cover the 64 banks once, whatever NG.  A DMA instruction fills whole
+// windows: 4 k x 16 rows (4-byte lanes) or 4 k x 64 rows (16-byte lanes).
+template <bool VEC, bool ONES>
 struct SRc {
   const float *p;
   int64_t ld, rows, ones;
   int orel = -1;  // row `ones` relative to the bound tile, -1 if outside
   static constexpr int kUnit = VEC ? 16 : 4;
+  static constexpr bool kOnes = ONES;  // the operand may hold the ones row
   template <int BR>
   static constexpr int bytes() { return BR * SBK * 4; }
   template <int BR>
   static constexpr int slots() { return bytes<BR>() / kUnit; }
-  __device__ static int hk(int k) { return ((k >> 2) ^ (k >> 3)) & 1; }
-  // rows beyond the matrix (the ones row among them: its fragments are set
-  // in registers) copy the last row, or for 16-byte lanes the last chunk
+  // rows beyond the matrix (the ones row among them) copy the last row, or
+  // for 16-byte lanes the last chunk
   static constexpr int kLast = VEC ? 4 : 1;
   __device__ int64_t clamp(int64_t gr) const { return gr < rows ? gr : rows - kLast; }
   // A tile may start at or past the last row (the ones row is row `rows`),
@@ -188,70 +196,70 @@ struct SRc {
   __device__ const char *base(int64_t r0, int k0) const {
     return reinterpret_cast<const char *>(p + (int64_t)k0 * ld + rbase(r0));
   }
+  // (k, first row) within the stage and tile of slot s
+  template <int BR>
+  __device__ static void slot_kr(int s, int &k, int &r) {
+    static_assert(BR % 16 == 0, "row tile");
+    constexpr int NG = BR / 16;
+    const int w = VEC ? s >> 2 : s >> 4;
+    const int t = VEC ? (s & 3) << 2 : s & 15;
+    const int idx = w >> 2, c = w & 3;
+    const int hj = idx / NG, rg = idx - hj * NG;
+    const int h = hj >> 2, j = hj & 3;
+    k = 16 * h + 8 * (c >> 1) + 4 * ((c & 1) ^ h) + j;
+    r = 16 * rg + t;
+  }
   template <int BR>
   __device__ uint32_t lane_off(int s, int64_t r0) const {
-    static_assert(BR % 16 == 0, "row tile");
     int k, r;
-    if constexpr (VEC) {
-      constexpr int NC = BR / 4;
-      k = s / NC;
-      int rc = s - k * NC - 4 * hk(k);
-      if (rc < 0) rc += NC;
-      r = 4 * rc;
-    } else {
-      k = s / BR;
-      r = s - k * BR - 16 * hk(k);
-      if (r < 0) r += BR;
-    }
+    slot_kr<BR>(s, k, r);
     return (uint32_t)(((int64_t)k * ld + (clamp(r0 + r) - rbase(r0))) * 4);
   }
   template <int BR>
   __device__ static int k_of(int s) {
-    if constexpr (VEC) return s / (BR / 4);
-    else return s / BR;
+    int k, r;
+    slot_kr<BR>(s, k, r);
+    return k;
   }
   __device__ void bind(int64_t r0) {
     const int64_t ro = ones - r0;
     orel = ones >= 0 && ro >= 0 && ro < 1 << 20 ? (int)ro : -1;
   }
-  // the ones row, for every k: a whole fragment of ones (the other operand
-  // is zero beyond the range, so the padding contributes nothing)
-  __device__ bool ones_group(int rg) const { return orel >= 16 * rg && orel < 16 * rg + 16; }
+  // Element (k = 16 h + 4 q + j, row 16 rg + q16) sits at float
+  // 64 ((4 h + j) NG + rg) + 16 c(k) + q16: a per-lane part (h, c, q16), a
+  // wave-uniform part (rg) and a constant (j), added in that order so that
+  // the constant stays an instruction offset.
+  // BF16 fragments of the ones row are set to ones here (FP32 sums instead)
+  __device__ bool ones_lane(int rg, int q16) const { return ONES && orel >= 0 && orel == 16 * rg + q16; }
   template <int BR>
   __device__ bf16x8 frag(const char *lds, int rg, int q16, int g4) const {
-    bf16x8 v = frag_lds<BR>(lds, rg, q16, g4);
-    if (ones_group(rg) && q16 == orel - 16 * rg) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = (__bf16)1.0f;
-    }
-    return v;
-  }
-  template <int BR>
-  __device__ bf16x8 frag_lds(const char *lds, int rg, int q16, int g4) const {
     constexpr int NG = BR / 16;
-    const float *t = reinterpret_cast<const float *>(lds);
-    // h(8 g4 + e) = (e >> 2) ^ (g4 & 1): position group rg + h (mod NG)
-    const int nxt = rg + 1 == NG ? 0 : rg + 1;
-    const int glo = (g4 & 1) ? nxt : rg, ghi = (g4 & 1) ? rg : nxt;
+    const float *t = reinterpret_cast<const float *>(lds) + 64 * rg;
+    // k = 8 g4 + e: h = g4 >> 1, bit 3 = g4 & 1, bit 2 = 0 (lo) or 1 (hi)
+    const int h = g4 >> 1, c = 2 * (g4 & 1);
+    const float *lo_p = t + (256 * NG * h + 16 * (c + h) + q16);
+    const float *hi_p = t + (256 * NG * h + 16 * (c + (1 ^ h)) + q16);
     floatx4 lo, hi;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      lo[e] = t[(8 * g4 + e) * BR + glo * 16 + q16];
-      hi[e] = t[(8 * g4 + 4 + e) * BR + ghi * 16 + q16];
+      lo[e] = lo_p[64 * NG * e];
+      hi[e] = hi_p[64 * NG * e];
     }
-    return to_bf16x8(lo, hi);
+    bf16x8 v = to_bf16x8(lo, hi);
+    if (ones_lane(rg, q16))
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (__bf16)1.0f;
+    return v;
   }
   template <int BR>
   __device__ floatx4 frag4(const char *lds, int rg, int q16, int g4, int h) const {
     constexpr int NG = BR / 16;
-    const float *t = reinterpret_cast<const float *>(lds);
-    // k = 16 h + 4 g4 + j: h(k) = (g4 ^ (g4 >> 1)) & 1 for every j
-    int pg = rg + ((g4 ^ (g4 >> 1)) & 1);
-    if (pg == NG) pg = 0;
+    // k = 16 h + 4 g4 + j: bit 2 = g4 & 1, bit 3 = g4 >> 1
+    const int c = 2 * (g4 >> 1) + ((g4 & 1) ^ h);
+    const float *p0 = reinterpret_cast<const float *>(lds) + 64 * rg + (256 * NG * h + 16 * c + q16);
     floatx4 v;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = t[(16 * h + 4 * g4 + j) * BR + pg * 16 + q16];
-    if (ones_group(rg) && q16 == orel - 16 * rg) v = floatx4{1.f, 1.f, 1.f, 1.f};
+    for (int j = 0; j < 4; ++j) v[j] = p0[64 * NG * j];
     return v;
   }
 };
@@ -263,6 +271,7 @@ struct SKh {
   const uint16_t *p;
   int64_t ldp, rows;
   static constexpr int kUnit = 16;
+  static constexpr bool kOnes = false;
   template <int BR>
   static constexpr int bytes() { return BR * SBK * 2; }
   template <int BR>
@@ -301,16 +310,18 @@ struct SKb : SKh {
 
 // bfloat16 row-contiguous (activations stored in bfloat16, reduced over
 // voxels): element (r, k) at p[k * ld + r], valid for r < rows, k < kend;
-// row `ones` (if >= 0) reads as 1 (set in registers, as in SRc).  A 16-byte
+// with ONES, row `ones` (if >= 0) stands for a row of ones, as in SRc.  A 16-byte
 // lane copies 8 consecutive rows of one k, so ld and rows are multiples of 8
 // and k-lines are 16-byte aligned.  LDS: [32][BR] bf16; the 8-row chunk c of
 // k-line k sits at chunk (c + 2 g(k)) mod (BR / 8), g(k) = (k >> 3) & 3, so
 // the four k of one fragment read (8 g4 + e, g4 = 0..3) land 32 bytes apart.
+template <bool ONES>
 struct SRb {
   const uint16_t *p;
   int64_t ld, rows, ones;
   int orel = -1;
   static constexpr int kUnit = 16;
+  static constexpr bool kOnes = ONES;
   template <int BR>
   static constexpr int bytes() { return BR * SBK * 2; }
   template <int BR>
@@ -337,7 +348,6 @@ struct SRb {
     const int64_t ro = ones - r0;
     orel = ones >= 0 && ro >= 0 && ro < 1 << 20 ? (int)ro : -1;
   }
-  __device__ bool ones_group(int rg) const { return orel >= 16 * rg && orel < 16 * rg + 16; }
   template <int BR>
   __device__ bf16x8 frag(const char *lds, int rg, int q16, int g4) const {
     constexpr int NC = BR / 8;
@@ -348,10 +358,9 @@ struct SRb {
     bf16x8 v;
 #pragma unroll
     for (int e = 0; e < 8; ++e) v[e] = __builtin_bit_cast(__bf16, t[(8 * g4 + e) * BR + pc * 8 + w]);
-    if (ones_group(rg) && q16 == orel - 16 * rg) {
+    if (ONES && orel >= 0 && orel == r)  // the ones row (a BF16 fragment: set here)
 #pragma unroll
       for (int e = 0; e < 8; ++e) v[e] = (__bf16)1.0f;
-    }
     return v;
   }
 };
@@ -366,12 +375,33 @@ struct SCfg {
   static_assert(NS >= 2 && NS <= 4, "ring depth");
 };
 
+// Sums standing in for the weight gradient's ones row in FP32.  The MFMAs
+// read that row's slots as copied (a clamped row), so the wave whose tiles
+// hold the row adds up the other operand's fragments instead: rs[i] the
+// k-sums of its A rows (ones row in B: an output column), cs[j] those of
+// its B rows (ones row in A: an output row), per lane over the lane's k;
+// the epilogue finishes the sums across lanes and stores them in place of
+// the row's MFMA results.  Flags are wave-uniform.  (Setting the row's
+// fragments to ones instead costs a select per fragment value: 44 per 72
+// MFMAs in the 128 x 144 tile.  BF16, bound by memory rather than by the
+// matrix cores, keeps those selects, which measured faster there than the
+// sums.)
+template <class CF>
+struct OnesSum {
+  bool a_on = false, b_on = false;  // ones row in this wave's A / B tiles
+  int rel = 0;                      // its row, relative to the wave's first row on that side
+  float rs[CF::TM], cs[CF::TN];
+};
+
+__device__ __forceinline__ float sum4(floatx4 v) { return (v[0] + v[1]) + (v[2] + v[3]); }
+
 // One stage (32 k) of MFMAs for a wave's TM x TN tiles.  FP32 runs the
 // stage's nh (1 or 2) groups of 16 k through one MFMA sequence (a last stage
 // ending within its first group needs one); BF16 ignores nh.
 template <class CF, bool F32, class AO, class BO>
 __device__ __forceinline__ void mma_stage(const AO &ao, const BO &bo, const char *sa, const char *sb, int wm, int wn,
-                                          int q16, int g4, int nh, floatx4 (&acc)[CF::TM][CF::TN]) {
+                                          int q16, int g4, int nh, floatx4 (&acc)[CF::TM][CF::TN],
+                                          OnesSum<CF> &os) {
   constexpr int BM = CF::BM, BN = CF::BN;
   if constexpr (F32) {
 #pragma unroll 1
@@ -381,6 +411,13 @@ __device__ __forceinline__ void mma_stage(const AO &ao, const BO &bo, const char
       for (int i = 0; i < CF::TM; ++i) a[i] = ao.template frag4<BM>(sa, wm * CF::TM + i, q16, g4, h);
 #pragma unroll
       for (int j = 0; j < CF::TN; ++j) b[j] = bo.template frag4<BN>(sb, wn * CF::TN + j, q16, g4, h);
+      if constexpr (BO::kOnes)  // every wave of a tile with the ones column: no branch
+#pragma unroll
+        for (int i = 0; i < CF::TM; ++i) os.rs[i] += sum4(a[i]);
+      if constexpr (AO::kOnes)
+        if (os.a_on)
+#pragma unroll
+          for (int j = 0; j < CF::TN; ++j) os.cs[j] += sum4(b[j]);
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj)
 #pragma unroll
@@ -400,6 +437,64 @@ __device__ __forceinline__ void mma_stage(const AO &ao, const BO &bo, const char
 #pragma unroll
       for (int j = 0; j < CF::TN; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j], a[i], acc[i][j], 0, 0, 0);
+  }
+}
+
+// Start the ones-row sums of a wave: locate the row in its A or B tiles.
+template <class CF, class AO, class BO>
+__device__ __forceinline__ void ones_begin(const AO &aw, const BO &bw, int wm, int wn, OnesSum<CF> &os) {
+  static_assert(!(AO::kOnes && BO::kOnes), "one operand with a ones row");
+  if constexpr (AO::kOnes) {
+    os.rel = aw.orel - wm * CF::TM * 16;
+    os.a_on = aw.orel >= 0 && os.rel >= 0 && os.rel < CF::TM * 16;
+  }
+  if constexpr (BO::kOnes) {
+    os.rel = bw.orel - wn * CF::TN * 16;
+    os.b_on = bw.orel >= 0 && os.rel >= 0 && os.rel < CF::TN * 16;
+  }
+#pragma unroll
+  for (int i = 0; i < CF::TM; ++i) os.rs[i] = 0.f;
+#pragma unroll
+  for (int j = 0; j < CF::TN; ++j) os.cs[j] = 0.f;
+}
+
+// Finish the sums across the four lanes of a row (lanes q16 + 16 g4 hold
+// disjoint k) and store them in place of the ones row's MFMA results: a
+// ones row in B is output column `rel` (lane (q16, g4) holds columns
+// 4 g4 .. 4 g4 + 3 of each 16-column tile), a ones row in A is output row
+// `rel`, whose column n of tile j is the sum lane q16 = n holds.
+template <class CF>
+__device__ __forceinline__ void ones_end(OnesSum<CF> &os, floatx4 (&acc)[CF::TM][CF::TN], int q16, int g4) {
+  if (os.b_on) {
+    const int jo = os.rel >> 4, go = (os.rel & 15) >> 2, eo = os.rel & 3;
+#pragma unroll
+    for (int i = 0; i < CF::TM; ++i) {
+      float r = os.rs[i];
+      r += __shfl_xor(r, 16);
+      r += __shfl_xor(r, 32);
+#pragma unroll
+      for (int j = 0; j < CF::TN; ++j)
+        if (j == jo && g4 == go)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (e == eo) acc[i][j][e] = r;
+    }
+  }
+  if (os.a_on) {
+    const int io = os.rel >> 4, qo = os.rel & 15;
+#pragma unroll
+    for (int j = 0; j < CF::TN; ++j) {
+      float c = os.cs[j];
+      c += __shfl_xor(c, 16);
+      c += __shfl_xor(c, 32);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float v = __shfl(c, 4 * g4 + e);
+#pragma unroll
+        for (int i = 0; i < CF::TM; ++i)
+          if (i == io && q16 == qo) acc[i][j][e] = v;
+      }
+    }
   }
 }
 
@@ -633,6 +728,8 @@ __global__ __launch_bounds__(256) void gemm_stream_kernel(AO ao, BO bo, CS cs, i
   BO bw = bo;
   aw.bind(m0);
   bw.bind(n0);
+  OnesSum<CF> os;
+  if constexpr (F32 && (AO::kOnes || BO::kOnes)) ones_begin<CF>(aw, bw, wm, wn, os);
   constexpr int NWA = dma_per_wave<BM, AO>(4), NWB = dma_per_wave<BN, BO>(4);
   uint32_t offa[NWA], offb[NWB];
   dma_offsets<BM>(ao, offa, wave, 4, lane, m0);
@@ -684,8 +781,9 @@ __global__ __launch_bounds__(256) void gemm_stream_kernel(AO ao, BO bo, CS cs, i
       if (it == side_it) load_side<CF>(cs, sp, M, N, m0, n0, wm, wn, q16, g4, z);
     const char *sa = lds + (it % NS) * SB;
     const int nh = kend - (kbeg + it * SBK) > 16 ? 2 : 1;
-    mma_stage<CF, F32>(aw, bw, sa, sa + AB, wm, wn, q16, g4, nh, acc);
+    mma_stage<CF, F32>(aw, bw, sa, sa + AB, wm, wn, q16, g4, nh, acc, os);
   }
+  if constexpr (F32 && (AO::kOnes || BO::kOnes)) ones_end<CF>(os, acc, q16, g4);
   if constexpr (SidePre<CF, CS>::kOn)
     if (niter == 0) load_side<CF>(cs, sp, M, N, m0, n0, wm, wn, q16, g4, z);
   store_tiles<CF>(cs, acc, M, N, m0, n0, wm, wn, q16, g4, z, sp);
@@ -1480,18 +1578,18 @@ template <bool F32, class GO>
 static int grad_act(GO go, const float *a, const uint16_t *ah, const GradArgs &x) {
   const int CK = x.CK;
   if constexpr (!F32)
-    if (ah) return grad_orient<F32>(go, SRb{ah, CK, CK, CK}, x);
-  if (CK % 4 == 0 && aligned16(a)) return grad_orient<F32>(go, SRc<true>{a, CK, CK, CK}, x);
-  return grad_orient<F32>(go, SRc<false>{a, CK, CK, CK}, x);
+    if (ah) return grad_orient<F32>(go, SRb<true>{ah, CK, CK, CK}, x);
+  if (CK % 4 == 0 && aligned16(a)) return grad_orient<F32>(go, SRc<true, true>{a, CK, CK, CK}, x);
+  return grad_orient<F32>(go, SRc<false, true>{a, CK, CK, CK}, x);
 }
 
 template <bool F32>
 static int stream_grad_p(const float *g, const uint16_t *gh, const float *a, const uint16_t *ah, const GradArgs &x) {
   const int M = x.M;
   if constexpr (!F32)
-    if (gh) return grad_act<F32>(SRb{gh, M, M, -1}, a, ah, x);
-  if (M % 4 == 0 && aligned16(g)) return grad_act<F32>(SRc<true>{g, M, M, -1}, a, ah, x);
-  return grad_act<F32>(SRc<false>{g, M, M, -1}, a, ah, x);
+    if (gh) return grad_act<F32>(SRb<false>{gh, M, M, -1}, a, ah, x);
+  if (M % 4 == 0 && aligned16(g)) return grad_act<F32>(SRc<true, false>{g, M, M, -1}, a, ah, x);
+  return grad_act<F32>(SRc<false, false>{g, M, M, -1}, a, ah, x);
 }
 
 bool stream_grad_ok(int M, int CK, int ksplit) {

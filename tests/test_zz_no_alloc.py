@@ -96,10 +96,21 @@ def test_noalloc_loss_head_refuses_batches_beyond_its_scratch():
     lib = dl.lib()
     cap = lib.dlm_sh2signal_mse_static_scratch_bytes()
     assert cap == 4 << 20
-    # the largest batch that fits, and one more 16-voxel tile
-    V = 16 * ((cap // 4 - 256) // 3)
+    # the largest batch that fits (the workspace grows with V), and one more
+    # 16-voxel tile
+    lo, hi = 16, 16
+    while lib.dlm_sh2signal_mse_workspace_bytes(plan.handle, hi) <= cap:
+        lo, hi = hi, 2 * hi
+    while hi - lo > 16:
+        mid = (lo + hi) // 32 * 16
+        if lib.dlm_sh2signal_mse_workspace_bytes(plan.handle, mid) <= cap:
+            lo = mid
+        else:
+            hi = mid
+    V = lo
     assert lib.dlm_sh2signal_mse_workspace_bytes(plan.handle, V) <= cap
     assert lib.dlm_sh2signal_mse_workspace_bytes(plan.handle, V + 16) > cap
+    assert V > 5_000_000  # a million-voxel batch fits many times over
     dummy = torch.zeros(16, device=DEV)
     st = lib.dlm_sh2signal_mse_fwd_bwd_noalloc(plan.handle, _p(dummy), _p(dummy), V + 16, _p(dummy), _p(dummy), None,
                                                 DLM_FP32, _stream())
