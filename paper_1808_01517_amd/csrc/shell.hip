@@ -13,7 +13,15 @@
 //   all issued before the first MFMA), so there is no LDS staging and no
 //   barrier, and many resident waves hide the latency;
 // * the table Bt_g arrives pre-arranged on the host in MFMA fragment order,
-//   one 16-byte load per lane per fragment (it stays in L1/L2);
+//   one 16-byte load per lane per fragment (it stays in L1/L2).  The FP32
+//   loss head on large batches runs as persistent 1024-thread blocks that
+//   first copy every shell's two fragment tables into LDS and then loop
+//   over wave items: its waves re-read ~36 KB of tables per 16 voxels x
+//   shell, more than 3x the voxels' own HBM traffic, and from L1/L2 that
+//   bound the FP32 MFMAs (1.00 -> 0.70 ms on the three-shell batch).  The
+//   same resident form measured slower for the BF16 head and for the
+//   standalone contractions, which are bound by memory latency instead,
+//   so those keep the short blocks;
 // * BF16: v_mfma_f32_16x16x32_bf16, lane (q16, g4) holds k = 32 s + 8 g4 .. + 7;
 //   FP32: v_mfma_f32_16x16x4_f32 over 16-k groups, lane (q16, g4) holds
 //   k = 16 h + 4 g4 .. + 3 and MFMA e takes k = 16 h + 4 g4 + e;
@@ -22,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "gemm_common.h"
 #include "internal.h"
@@ -320,6 +329,172 @@ __global__ __launch_bounds__(256) void sh2s_mse_kernel(const float *c, int64_t l
   }
 }
 
+
+// One FP32 wave item of the loss head (w = rb * groups + g), the FP32 branch
+// of sh2s_mse_kernel with the fragment tables in the block's LDS copy.
+__device__ __forceinline__ void sh2s_mse_item_f32(const float *c, int64_t ldcoef, int K, const float *tgt,
+                                                  int64_t ldsig, int N, float *dc, float *xhat, const char *fragB,
+                                                  const char *fragBt, int64_t gsB, int64_t gsBt, int groups, int64_t V,
+                                                  int64_t w, float scale, float *partials) {
+  const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
+  const int64_t rb = w / groups;
+  const int g = (int)(w - rb * groups);
+  const int64_t r = rb * 16 + q16;
+  const bool row = r < V;
+  const float *a = c + r * ldcoef + (int64_t)g * K;
+  const float *t = tgt + r * ldsig + (int64_t)g * N;
+  const int NT1 = (N + 15) / 16, NT2 = (K + 15) / 16;
+  floatx4 acc[kColChunk], acc2[4];
+#pragma unroll
+  for (int j = 0; j < kColChunk; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc2[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  // target values of this lane's accumulator positions, loaded up front
+  floatx4 tv[kColChunk];
+#pragma unroll
+  for (int j = 0; j < kColChunk; ++j)
+    tv[j] = j < NT1 ? load_run(t, 16 * j + 4 * g4, N, row) : floatx4{0.f, 0.f, 0.f, 0.f};
+  {
+    const floatx4 *f1 = reinterpret_cast<const floatx4 *>(fragB + (int64_t)g * gsB);
+    const floatx4 *f2 = reinterpret_cast<const floatx4 *>(fragBt + (int64_t)g * gsBt);
+    const int H = (K + 15) / 16;
+    floatx4 av[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) av[h] = h < H ? load_run(a, 16 * h + 4 * g4, K, row) : floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      if (h >= H) break;
+#pragma unroll
+      for (int j = 0; j < kColChunk; ++j) {
+        if (j >= NT1) break;
+        const floatx4 b = f1[((int64_t)j * H + h) * 64 + lane];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[e], av[h][e], acc[j], 0, 0, 0);
+      }
+    }
+    float lsum = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kColChunk; ++j) {
+      if (j >= NT1) break;
+      const int n = 16 * j + 4 * g4;
+      if (xhat && row) {
+        float *xo = xhat + r * ldsig + (int64_t)g * N;
+        if (n + 3 < N) __builtin_memcpy(xo + n, &acc[j], 16);
+        else
+          for (int e = 0; e < 4; ++e)
+            if (n + e < N) xo[n + e] = acc[j][e];
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float diff = row && n + e < N ? acc[j][e] - tv[j][e] : 0.0f;
+        lsum += diff * diff;
+        acc[j][e] = diff * scale;  // now d
+      }
+    }
+    // GEMM 2 over n: group h of 16 n = accumulator tile h
+#pragma unroll
+    for (int h = 0; h < kColChunk; ++h) {
+      if (h >= NT1) break;
+#pragma unroll
+      for (int j2 = 0; j2 < 4; ++j2) {
+        if (j2 >= NT2) break;
+        const floatx4 b = f2[((int64_t)j2 * NT1 + h) * 64 + lane];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc2[j2] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[e], acc[h][e], acc2[j2], 0, 0, 0);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+    if (lane == 0) partials[w] = lsum;
+  }
+  if (row) {
+    float *o = dc + r * ldcoef + (int64_t)g * K;
+#pragma unroll
+    for (int j2 = 0; j2 < 4; ++j2) {
+      if (j2 >= NT2) break;
+      const int k = 16 * j2 + 4 * g4;
+      if (k + 3 < K) __builtin_memcpy(o + k, &acc2[j2], 16);
+      else
+        for (int e = 0; e < 4; ++e)
+          if (k + e < K) o[k + e] = acc2[j2][e];
+    }
+  }
+}
+
+
+// Table-resident form: kResWaves waves per block; the block copies the
+// fragment tables (a multiple of 16 bytes) into LDS, then each wave takes
+// items w = blockIdx.x * kResWaves + wave, stepping by the grid.
+constexpr int kResWaves = 16;
+
+__device__ __forceinline__ void copy_to_lds(char *dst, const void *src, int64_t bytes) {
+  const uint4 *s4 = static_cast<const uint4 *>(src);
+  uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+  for (int64_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) d4[i] = s4[i];
+}
+
+// Compute units of the current device (cached per device).
+int device_cus() {
+  static int cus[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (!cus[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    cus[dev] = n;
+  }
+  return cus[dev];
+}
+
+// LDS the table-resident blocks may take, and the least number of wave
+// items per block for them to pay (below it the short-block form runs).
+constexpr int64_t kResLdsMax = 150 * 1024;
+constexpr int64_t kResMinItems = 4 * kResWaves;
+
+// Grid of the table-resident form for nwaves items and tab_bytes of tables:
+// as many blocks as fit on every compute unit at once (registers and LDS
+// decide), or 0 when the short-block form should run.
+// DLM_SHELL_RESIDENT=0 in the environment (read at each launch) selects the
+// short-block form everywhere, so that tests can compare the two.
+template <class KERNEL>
+int res_grid(KERNEL kernel, int64_t nwaves, int64_t tab_bytes) {
+  const char *env = std::getenv("DLM_SHELL_RESIDENT");
+  if (env && env[0] == '0') return 0;
+  if (tab_bytes > kResLdsMax || tab_bytes % 16 != 0) return 0;
+  const int cus = device_cus();
+  if (cus <= 0 || nwaves < kResMinItems * cus) return 0;
+  if (tab_bytes > 64 * 1024 &&
+      hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)tab_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64 * kResWaves, (size_t)tab_bytes) != hipSuccess ||
+      per_cu <= 0) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  if (nwaves < kResMinItems * cus * per_cu) per_cu = 1;
+  return cus * per_cu;
+}
+
+// Table-resident FP32 loss head: both tables of every shell in LDS, B's
+// first (groups * gsB bytes), then B^T's.
+__global__ __launch_bounds__(1024) void sh2s_mse_res_kernel(const float *c, int64_t ldcoef, int K, const float *tgt,
+                                                            int64_t ldsig, int N, float *dc, float *xhat,
+                                                            const void *fragB, const void *fragBt, int64_t gsB,
+                                                            int64_t gsBt, int groups, int64_t V, int64_t nwaves,
+                                                            float scale, float *partials) {
+  extern __shared__ __attribute__((aligned(16))) char tab[];
+  copy_to_lds(tab, fragB, gsB * groups);
+  copy_to_lds(tab + gsB * groups, fragBt, gsBt * groups);
+  __syncthreads();
+  const int64_t step = (int64_t)gridDim.x * kResWaves;
+  for (int64_t w = (int64_t)blockIdx.x * kResWaves + (threadIdx.x >> 6); w < nwaves; w += step)
+    sh2s_mse_item_f32(c, ldcoef, K, tgt, ldsig, N, dc, xhat, tab, tab + gsB * groups, gsB, gsBt, groups, V, w, scale,
+                      partials);
+}
+
 }  // namespace shellk
 
 bool sh2s_mse_ok(int N, int K) { return N > 0 && N <= 16 * shellk::kColChunk && K > 0 && K <= 64; }
@@ -333,10 +508,18 @@ int launch_sh2s_mse(const Sh2sMse &t, dlm_precision prec, void *stream) {
   const int64_t nwaves = sh2s_mse_partials(t.V, t.groups);
   const int64_t blocks = (nwaves + 3) / 4;
   if (blocks > 0x7fffffff) return -4;
-  if (prec == DLM_BF16)
+  if (prec == DLM_BF16) {
     hipLaunchKernelGGL((shellk::sh2s_mse_kernel<false>), dim3((unsigned)blocks), dim3(256), 0, st, t.c, t.ldcoef, t.K,
                        t.target, t.ldsig, t.N, t.dc, t.xhat, (const void *)t.fragB_h, (const void *)t.fragBt_h,
                        t.gsB_h, t.gsBt_h, t.groups, t.V, nwaves, t.scale, t.partials);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
+  const int64_t tab = (t.gsB_f + t.gsBt_f) * t.groups;
+  const int grid = shellk::res_grid(shellk::sh2s_mse_res_kernel, nwaves, tab);
+  if (grid > 0)
+    hipLaunchKernelGGL((shellk::sh2s_mse_res_kernel), dim3(grid), dim3(64 * shellk::kResWaves), tab, st, t.c,
+                       t.ldcoef, t.K, t.target, t.ldsig, t.N, t.dc, t.xhat, (const void *)t.fragB_f,
+                       (const void *)t.fragBt_f, t.gsB_f, t.gsBt_f, t.groups, t.V, nwaves, t.scale, t.partials);
   else
     hipLaunchKernelGGL((shellk::sh2s_mse_kernel<true>), dim3((unsigned)blocks), dim3(256), 0, st, t.c, t.ldcoef, t.K,
                        t.target, t.ldsig, t.N, t.dc, t.xhat, (const void *)t.fragB_f, (const void *)t.fragBt_f,
