@@ -520,21 +520,60 @@ int launch_table_gemm(const TableGemm &t, dlm_precision prec, void *stream) {
 }
 
 // --------------------------------------------- LSC neighbourhood contraction
+// Index arithmetic of the paper-order form: the neighbourhood matrices X
+// are [v][c][i][t] (m rows of T taps per voxel and channel), row-major, so
+// the contractions address them through (v, i) = divmod(r, m) and
+// (c, t) = divmod(k, T).  FastDiv divides by such a divisor with one 64-bit
+// multiply and a shift (the round-up reciprocal mul = ceil(2^(32+s) / d),
+// s = ceil(log2 d), exact for every dividend below 2^31 because 2^s >= d;
+// the launchers keep row and reduction counts below 2^31).  Runs of 4
+// entries that lie inside one T-tap segment (or inside one voxel's m rows)
+// move as one 16-byte access; only runs across a boundary go entry by entry.
+struct FastDiv {
+  uint64_t mul = uint64_t(1) << 32;
+  int shift = 32;
+  int d = 1;
+  static FastDiv make(int d) {
+    FastDiv f;
+    int s = 0;
+    while ((int64_t(1) << s) < d) ++s;
+    f.d = d;
+    f.shift = 32 + s;
+    f.mul = ((uint64_t(1) << f.shift) + uint64_t(d) - 1) / uint64_t(d);
+    return f;
+  }
+  __device__ int div(int n) const { return (int)(((uint64_t)(uint32_t)n * mul) >> shift); }
+};
+
+__device__ __forceinline__ void st4(float *p, floatx4 v) {
+  __builtin_memcpy(p, &v, 16);  // dword-aligned 16-byte store
+}
+
 // Row r = (v, i) of the neighbourhood matrix; column k = (c, t).
 struct ANbhd {
   static constexpr bool kContig = true;
   static constexpr bool kMask = false;
   const float *X;
   int m, T, C;
-  __device__ float operator()(int64_t r, int k, int) const {
-    const int64_t v = r / m;
-    const int i = (int)(r - v * m);
-    const int c = k / T, t = k - c * T;
-    const int64_t P = (int64_t)m * T;
-    return X[(v * C + c) * P + (int64_t)i * T + t];
+  FastDiv fm, fT;
+  __device__ const float *row(int64_t r, int c, int t) const {
+    const int v = fm.div((int)r), i = (int)r - v * m;
+    return X + ((int64_t)v * C + c) * ((int64_t)m * T) + (int64_t)i * T + t;
   }
-  __device__ floatx4 load4(int64_t r, int k, int g) const {
-    return floatx4{(*this)(r, k, g), (*this)(r, k + 1, g), (*this)(r, k + 2, g), (*this)(r, k + 3, g)};
+  __device__ float operator()(int64_t r, int k, int) const {
+    const int c = fT.div(k), t = k - c * T;
+    return *row(r, c, t);
+  }
+  __device__ floatx4 load4(int64_t r, int k, int) const {
+    const int c = fT.div(k), t = k - c * T;
+    const float *p = row(r, c, t);
+    if (t + 3 < T) return ld4(p);
+    // the run crosses into channel c + 1 (k + 3 < C T is the caller's range)
+    const int64_t next = (int64_t)m * T - T;  // from (c, T) to (c + 1, 0) in the same row i
+    floatx4 v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = t + e < T ? p[e] : p[e + next];
+    return v;
   }
 };
 
@@ -562,18 +601,23 @@ struct BWeightH {
   }
 };
 
+// y[v][o][i] for row r = (v, i), column o: four columns are m apart (the
+// lanes of a wave hold consecutive rows, so each store is coalesced).
 struct CSignalY {
   float *y;
   const float *bias;
   int m, O;
+  FastDiv fm;
   __device__ void operator()(int64_t r, int o, int, float v) const {
-    const int64_t vx = r / m;
-    const int i = (int)(r - vx * m);
+    const int vx = fm.div((int)r), i = (int)r - vx * m;
     if (bias) v += bias[o];
-    y[(vx * O + o) * m + i] = v;
+    y[((int64_t)vx * O + o) * m + i] = v;
   }
-  __device__ void store4(int64_t r, int n, int g, floatx4 v) const {
-    for (int q = 0; q < 4; ++q) (*this)(r, n + q, g, v[q]);
+  __device__ void store4(int64_t r, int n, int, floatx4 v) const {
+    const int vx = fm.div((int)r), i = (int)r - vx * m;
+    float *p = y + ((int64_t)vx * O + n) * m + i;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) p[(int64_t)q * m] = v[q] + (bias ? bias[n + q] : 0.0f);
   }
 };
 
@@ -582,8 +626,9 @@ int launch_lsc_contract_fwd(const float *X, const float *W, const uint16_t *Wh, 
   hipStream_t st = (hipStream_t)stream;
   const int64_t M = V * m;
   const int K = C * T;
-  ANbhd al{X, m, T, C};
-  CSignalY cs{y, bias, m, O};
+  if (M >= (int64_t(1) << 31)) return -4;
+  ANbhd al{X, m, T, C, FastDiv::make(m), FastDiv::make(T)};
+  CSignalY cs{y, bias, m, O, FastDiv::make(m)};
   const Shape sh = pick_shape(O);
   if (prec == DLM_BF16) return run_gemm_p<kOpContractFwd, true>(al, BWeightH{Wh, K}, cs, M, O, K, 1, 0, st, sh);
   return run_gemm_p<kOpContractFwd, false>(al, BWeightF{W, K}, cs, M, O, K, 1, 0, st, sh);
@@ -596,12 +641,14 @@ struct ADy {
   static constexpr bool kMask = false;
   const float *dy;
   int m, O;
+  FastDiv fm;
   __device__ float operator()(int64_t r, int o, int) const {
-    const int64_t v = r / m;
-    const int i = (int)(r - v * m);
-    return dy[(v * O + o) * m + i];
+    const int v = fm.div((int)r), i = (int)r - v * m;
+    return dy[((int64_t)v * O + o) * m + i];
   }
   __device__ floatx4 load4(int64_t r, int o, int g) const {
+    const int v = fm.div((int)r), i = (int)r - v * m;
+    if (i + 3 < m) return ld4(dy + ((int64_t)v * O + o) * m + i);  // four rows of one voxel
     return floatx4{(*this)(r, o, g), (*this)(r + 1, o, g), (*this)(r + 2, o, g), (*this)(r + 3, o, g)};
   }
 };
@@ -609,15 +656,20 @@ struct ADy {
 struct CNbhd {
   float *dX;
   int m, T, C;
-  __device__ void operator()(int64_t r, int n, int, float val) const {
-    const int64_t v = r / m;
-    const int i = (int)(r - v * m);
-    const int c = n / T, t = n - c * T;
-    const int64_t P = (int64_t)m * T;
-    dX[(v * C + c) * P + (int64_t)i * T + t] = val;
+  FastDiv fm, fT;
+  __device__ float *at(int64_t r, int n) const {
+    const int v = fm.div((int)r), i = (int)r - v * m;
+    const int c = fT.div(n), t = n - c * T;
+    return dX + ((int64_t)v * C + c) * ((int64_t)m * T) + (int64_t)i * T + t;
   }
+  __device__ void operator()(int64_t r, int n, int, float val) const { *at(r, n) = val; }
   __device__ void store4(int64_t r, int n, int g, floatx4 v) const {
-    for (int q = 0; q < 4; ++q) (*this)(r, n + q, g, v[q]);
+    const int t = n - fT.div(n) * T;
+    if (t + 3 < T) {
+      st4(at(r, n), v);
+    } else {
+      for (int q = 0; q < 4; ++q) (*this)(r, n + q, g, v[q]);
+    }
   }
 };
 
@@ -626,8 +678,9 @@ int launch_lsc_contract_bwd_data(const float *dy, const float *Wt, const uint16_
   hipStream_t st = (hipStream_t)stream;
   const int64_t M = V * m;
   const int N = C * T;
-  ADy al{dy, m, O};
-  CNbhd cs{dX, m, T, C};
+  if (M >= (int64_t(1) << 31)) return -4;
+  ADy al{dy, m, O, FastDiv::make(m)};
+  CNbhd cs{dX, m, T, C, FastDiv::make(m), FastDiv::make(T)};
   const Shape sh = pick_shape(N);
   if (prec == DLM_BF16) return run_gemm_p<kOpContractBwdData, true>(al, BWeightH{Wth, O}, cs, M, N, O, 1, 0, st, sh);
   return run_gemm_p<kOpContractBwdData, false>(al, BWeightF{Wt, O}, cs, M, N, O, 1, 0, st, sh);
@@ -640,15 +693,22 @@ struct AXt {
   static constexpr bool kMask = false;
   const float *X;
   int m, T, C;
+  FastDiv fm, fT;
   __device__ float operator()(int64_t r, int k, int) const {
     const int CT = C * T;
     if (r == CT) return 1.0f;
-    const int v = k / m, i = k - v * m;
-    const int c = (int)r / T, t = (int)r - c * T;
-    const int64_t P = (int64_t)m * T;
-    return X[((int64_t)v * C + c) * P + (int64_t)i * T + t];
+    const int v = fm.div(k), i = k - v * m;
+    const int c = fT.div((int)r), t = (int)r - c * T;
+    return X[((int64_t)v * C + c) * ((int64_t)m * T) + (int64_t)i * T + t];
   }
   __device__ floatx4 load4(int64_t r, int k, int g) const {
+    // four consecutive taps (c, t .. t+3) of one row i: contiguous inside a
+    // segment; the bias row r = C T and segment crossings go entry by entry
+    const int c = fT.div((int)r), t = (int)r - c * T;
+    if (t + 3 < T) {
+      const int v = fm.div(k), i = k - v * m;
+      return ld4(X + ((int64_t)v * C + c) * ((int64_t)m * T) + (int64_t)i * T + t);
+    }
     return floatx4{(*this)(r, k, g), (*this)(r + 1, k, g), (*this)(r + 2, k, g), (*this)(r + 3, k, g)};
   }
 };
@@ -659,11 +719,14 @@ struct BDyT {
   using type = float;
   const float *dy;
   int m, O;
+  FastDiv fm;
   __device__ float operator()(int o, int k, int) const {
-    const int v = k / m, i = k - v * m;
+    const int v = fm.div(k), i = k - v * m;
     return dy[((int64_t)v * O + o) * m + i];
   }
   __device__ floatx4 load4(int o, int k, int g) const {
+    const int v = fm.div(k), i = k - v * m;
+    if (i + 3 < m) return ld4(dy + ((int64_t)v * O + o) * m + i);  // four rows of one voxel
     return floatx4{(*this)(o, k, g), (*this)(o, k + 1, g), (*this)(o, k + 2, g), (*this)(o, k + 3, g)};
   }
 };
@@ -675,7 +738,7 @@ struct CPartial {
     part[((int64_t)s * rows + r) * O + o] = v;
   }
   __device__ void store4(int64_t r, int n, int g, floatx4 v) const {
-    for (int q = 0; q < 4; ++q) (*this)(r, n + q, g, v[q]);
+    st4(part + ((int64_t)g * rows + r) * O + n, v);  // n + 3 < O: four adjacent columns
   }
 };
 
@@ -691,8 +754,10 @@ int launch_lsc_contract_bwd_weight(const float *X, const float *dy, float *parti
   // splits beyond `used` would see an empty range; the caller sizes `splits`
   // so that every slice is non-empty and reduces exactly `splits` partials.
   if (used != splits) return -2;
-  return run_gemm<kOpContractBwdWeight>(AXt{X, m, T, C}, BDyT{dy, m, O}, CPartial{partial, rows, O}, rows, O, (int)Kfull, splits, ksplit,
-                  prec, st, pick_shape(O));
+  if (Kfull >= (int64_t(1) << 31)) return -4;
+  return run_gemm<kOpContractBwdWeight>(AXt{X, m, T, C, FastDiv::make(m), FastDiv::make(T)},
+                                        BDyT{dy, m, O, FastDiv::make(m)}, CPartial{partial, rows, O}, rows, O,
+                                        (int)Kfull, splits, ksplit, prec, st, pick_shape(O));
 }
 
 int lsc_weight_splits(int64_t V, int m, int target) {
