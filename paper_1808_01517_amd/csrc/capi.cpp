@@ -537,12 +537,14 @@ dlm_status sh_apply(const dlm_sh_plan *p, const float *in, float *out, int64_t V
     t.op = kops[int(op)];
     const double ng = double(t.groups);
     TimedScope ts(tags[int(op)], stream, double(V) * ng * (double(N) + K) * 4.0, 2.0 * double(V) * ng * N * K);
-    int rc;
+    int rc = 0;
     // one wave per 16 voxels x shell (tables in fragment order) for the
     // contractions over the coefficients (K <= 64: Signal2SH adjoint,
-    // SH2Signal); reductions over a shell's directions keep the tiled core,
-    // which measured faster for them
-    if (shell_gemm_ok(t.N, t.K) && t.K <= 64) {
+    // SH2Signal), and for FP32 Signal2SH on large batches in its
+    // table-resident form; other reductions over a shell's directions keep
+    // the tiled core, which measured faster for them
+    bool shell = false;
+    if (shell_gemm_ok(t.N, t.K)) {
       const int ti = int(op);
       ShellGemm g;
       g.A = t.A;
@@ -560,10 +562,10 @@ dlm_status sh_apply(const dlm_sh_plan *p, const float *in, float *out, int64_t V
       g.groups = t.groups;
       g.V = V;
       g.op = t.op;
-      rc = launch_shell_gemm(g, prec, stream);
-    } else {
-      rc = launch_table_gemm(t, prec, stream);
+      shell = t.K <= 64 || shell_s2sh_resident(g, prec);
+      if (shell) rc = launch_shell_gemm(g, prec, stream);
     }
+    if (!shell) rc = launch_table_gemm(t, prec, stream);
     if (rc != 0) return launched(rc);
   }
   return ok();

@@ -20,8 +20,11 @@
 //   shell, more than 3x the voxels' own HBM traffic, and from L1/L2 that
 //   bound the FP32 MFMAs (1.00 -> 0.70 ms on the three-shell batch).  The
 //   same resident form measured slower for the BF16 head and for the
-//   standalone contractions, which are bound by memory latency instead,
-//   so those keep the short blocks;
+//   contractions over the coefficients, which are bound by memory latency
+//   instead, so those keep the short blocks.  FP32 Signal2SH (the
+//   reduction over a shell's directions) gains from it when each wave
+//   also fetches its next item's rows ahead (0.575 -> 0.528 ms); it runs
+//   on the tiled core otherwise;
 // * BF16: v_mfma_f32_16x16x32_bf16, lane (q16, g4) holds k = 32 s + 8 g4 .. + 7;
 //   FP32: v_mfma_f32_16x16x4_f32 over 16-k groups, lane (q16, g4) holds
 //   k = 16 h + 4 g4 .. + 3 and MFMA e takes k = 16 h + 4 g4 + e;
@@ -495,7 +498,99 @@ __global__ __launch_bounds__(1024) void sh2s_mse_res_kernel(const float *c, int6
                       partials);
 }
 
+// Table-resident FP32 Signal2SH, the reduction over a shell's directions
+// (nred <= kMaxRed): persistent blocks as the resident loss head, and each
+// wave keeps one item ahead, issuing the next item's A loads before this
+// item's MFMAs.  The item arithmetic is shell_gemm_kernel's FP32 branch.
+// Where this form does not apply Signal2SH runs on the tiled core, whose
+// summation order differs: results agree to rounding, not bit for bit.
+struct RowsF32 {
+  floatx4 v[kMaxRed / 16];  // lane (q16, g4): k = 16 h + 4 g4 .. + 3 of its row
+};
+
+__device__ __forceinline__ void s2sh_load(RowsF32 &x, const float *A, int64_t lda, int64_t a_gs, int nred, int groups,
+                                          int64_t V, int64_t w) {
+  const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
+  const int64_t rb = w / groups;
+  const int g = (int)(w - rb * groups);
+  const int64_t r = rb * 16 + q16;
+  const float *a = A + r * lda + (int64_t)g * a_gs;
+  const int H = (nred + 15) / 16;
+#pragma unroll
+  for (int h = 0; h < kMaxRed / 16; ++h)
+    x.v[h] = h < H ? load_run(a, 16 * h + 4 * g4, nred, r < V) : floatx4{0.f, 0.f, 0.f, 0.f};
+}
+
+__device__ __forceinline__ void s2sh_compute(const RowsF32 &x, float *C, int64_t ldc, int64_t c_gs, const char *frag,
+                                             int64_t frag_gs, int ncol, int nred, int groups, int64_t V, int64_t w) {
+  const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
+  const int64_t rb = w / groups;
+  const int g = (int)(w - rb * groups);
+  const int64_t r = rb * 16 + q16;
+  float *c = C + r * ldc + (int64_t)g * c_gs;
+  const int NT = (ncol + 15) / 16, H = (nred + 15) / 16;
+  const floatx4 *fr = reinterpret_cast<const floatx4 *>(frag + (int64_t)g * frag_gs);
+  for (int j0 = 0; j0 < NT; j0 += kColChunk) {
+    const int nt = min(kColChunk, NT - j0);
+    floatx4 acc[kColChunk];
+#pragma unroll
+    for (int j = 0; j < kColChunk; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int h = 0; h < kMaxRed / 16; ++h) {
+      if (h >= H) break;
+#pragma unroll
+      for (int j = 0; j < kColChunk; ++j) {
+        if (j >= nt) break;
+        const floatx4 b = fr[((int64_t)(j0 + j) * H + h) * 64 + lane];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[e], x.v[h][e], acc[j], 0, 0, 0);
+      }
+    }
+    if (r < V) {
+#pragma unroll
+      for (int j = 0; j < kColChunk; ++j) {
+        if (j >= nt) break;
+        const int n = 16 * (j0 + j) + 4 * g4;
+        if (n + 3 < ncol) __builtin_memcpy(c + n, &acc[j], 16);
+        else
+          for (int e = 0; e < 4; ++e)
+            if (n + e < ncol) c[n + e] = acc[j][e];
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(1024) void s2sh_res_kernel(const float *A, int64_t lda, int64_t a_gs, float *C,
+                                                        int64_t ldc, int64_t c_gs, const void *frag, int64_t frag_gs,
+                                                        int ncol, int nred, int groups, int64_t V, int64_t nwaves) {
+  extern __shared__ __attribute__((aligned(16))) char tab[];
+  copy_to_lds(tab, frag, frag_gs * groups);
+  __syncthreads();
+  const int64_t step = (int64_t)gridDim.x * kResWaves;
+  int64_t w = (int64_t)blockIdx.x * kResWaves + (threadIdx.x >> 6);
+  if (w >= nwaves) return;  // no barrier follows
+  RowsF32 cur;
+  s2sh_load(cur, A, lda, a_gs, nred, groups, V, w);
+  for (; w < nwaves; w += step) {
+    RowsF32 nxt;
+    if (w + step < nwaves) s2sh_load(nxt, A, lda, a_gs, nred, groups, V, w + step);
+    s2sh_compute(cur, C, ldc, c_gs, tab, frag_gs, ncol, nred, groups, V, w);
+    cur = nxt;
+  }
+}
+
+// Grid of the resident FP32 Signal2SH for t, 0 when it does not apply.
+int s2sh_res_grid(const ShellGemm &t) {
+  const int64_t nwaves = (t.V + 15) / 16 * t.groups;
+  return res_grid(s2sh_res_kernel, nwaves, t.frag_gs_f * t.groups);
+}
+
 }  // namespace shellk
+
+bool shell_s2sh_resident(const ShellGemm &t, dlm_precision prec) {
+  return prec != DLM_BF16 && t.op == kOpS2shFwd && shell_gemm_ok(t.ncol, t.nred) && t.V > 0 &&
+         shellk::s2sh_res_grid(t) > 0;
+}
 
 bool sh2s_mse_ok(int N, int K) { return N > 0 && N <= 16 * shellk::kColChunk && K > 0 && K <= 64; }
 
@@ -534,7 +629,16 @@ int launch_shell_gemm(const ShellGemm &t, dlm_precision prec, void *stream) {
   if (t.V <= 0) return 0;
   hipStream_t st = (hipStream_t)stream;
   switch (t.op) {
-    case kOpS2shFwd: return shellk::launch_op<kOpS2shFwd>(t, prec, st);
+    case kOpS2shFwd:
+      if (shell_s2sh_resident(t, prec)) {
+        const int grid = shellk::s2sh_res_grid(t);
+        const int64_t nwaves = (t.V + 15) / 16 * t.groups;
+        hipLaunchKernelGGL(shellk::s2sh_res_kernel, dim3(grid), dim3(64 * shellk::kResWaves), t.frag_gs_f * t.groups,
+                           st, t.A, t.lda, t.a_gs, t.C, t.ldc, t.c_gs, (const void *)t.frag_f, t.frag_gs_f, t.ncol,
+                           t.nred, t.groups, t.V, nwaves);
+        return hipGetLastError() == hipSuccess ? 0 : -1;
+      }
+      return shellk::launch_op<kOpS2shFwd>(t, prec, st);
     case kOpS2shBwd: return shellk::launch_op<kOpS2shBwd>(t, prec, st);
     case kOpSh2sFwd: return shellk::launch_op<kOpSh2sFwd>(t, prec, st);
     case kOpSh2sBwd: return shellk::launch_op<kOpSh2sBwd>(t, prec, st);

@@ -1,13 +1,14 @@
-"""The FP32 loss head in its table-resident form (large batches: persistent
-blocks that copy every shell's fragment tables into LDS once) against its
-short-block form (small batches; DLM_SHELL_RESIDENT=0 forces it) and
-against the FP64 oracle, with the SH2Signal and Signal2SH-adjoint
-contractions of the same large batch beside it.
+"""The table-resident FP32 kernels (large batches: persistent blocks that
+copy every shell's fragment tables into LDS once) against their other forms
+(small batches; DLM_SHELL_RESIDENT=0 forces those) and against the FP64
+oracle: the loss head, and Signal2SH, with the SH2Signal and
+Signal2SH-adjoint contractions of the same large batch beside them.
 
-Both forms run the same per-item arithmetic on the same fragments, so they
-must agree bit for bit: loss, gradient and x^ (the BF16 head and the
-contractions have one form, so there the comparison is of a call with
-itself).  The batch (90,007 voxels of the three-shell 90-direction order-8
+The loss head's two forms run the same per-item arithmetic on the same
+fragments, so they must agree bit for bit: loss, gradient and x^ (the BF16
+head and the contractions over the coefficients have one form, so there
+the comparison is of a call with itself).  Signal2SH's other form is the
+tiled core, whose summation order differs: it is held to the oracle only.  The batch (90,007 voxels of the three-shell 90-direction order-8
 table) is large enough for the resident form and leaves a ragged 16-voxel
 tile; a batch of unequal shells (17/45/96, one launch per shell, 270,021
 voxels) takes it shell by shell.
@@ -48,11 +49,12 @@ def _acq(kind):
 
 
 def _run(plan, c, tgt, dcoef, prec):
+    coef = dl.signal2sh_fwd(plan, tgt, precision=prec) if plan.has_fit else None
     x = dl.sh2signal_fwd(plan, c, precision=prec)
     dx = dl.signal2sh_bwd(plan, dcoef, precision=prec)
     loss, dc, xhat = dl.sh2signal_mse_fwd_bwd(plan, c, tgt, need_xhat=True, precision=prec)
     torch.cuda.synchronize()
-    return x, dx, loss, dc, xhat
+    return x, dx, loss, dc, xhat, coef
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
@@ -74,10 +76,13 @@ def test_resident_tables_match_short_blocks_and_oracle(prec, kind):
         short = _run(plan, cg, tg, dg_, prec)
     finally:
         del os.environ["DLM_SHELL_RESIDENT"]
-    for name, a, b in zip(("x", "dx", "loss", "dc", "xhat"), res, short):
+    for name, a, b in zip(("x", "dx", "loss", "dc", "xhat"), res[:5], short[:5]):
         assert torch.equal(a, b), f"{kind} {prec}: {name} differs between the two forms"
-    x, dx, loss, dc, xhat = res
+    x, dx, loss, dc, xhat, coef = res
     errs = {}
+    c_ref = osh.signal2sh(oplan, tgt)
+    check("c", coef, c_ref, prec, errs)
+    check("c_other_form", short[5], c_ref, prec, errs)
     x_ref = osh.sh2signal(oplan, c)
     check("x", x, x_ref, prec, errs)
     check("dx", dx, osh.signal2sh_adjoint(oplan, dcoef), prec, errs)
