@@ -34,6 +34,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <mutex>
 
 #include "gemm_common.h"
 #include "internal.h"
@@ -457,7 +458,21 @@ constexpr int64_t kResMinItems = 4 * kResWaves;
 // as many blocks as fit on every compute unit at once (registers and LDS
 // decide), or 0 when the short-block form should run.
 // DLM_SHELL_RESIDENT=0 in the environment (read at each launch) selects the
-// short-block form everywhere, so that tests can compare the two.
+// short-block form everywhere, so that tests can compare the two.  The LDS
+// limit and the occupancy query are done once per device, kernel and table
+// size and then cached, so later launches make no such host calls.
+struct ResFit {
+  int dev = -1;
+  const void *kernel = nullptr;
+  int64_t bytes = 0;
+  int per_cu = 0;  // 0: does not fit
+};
+struct ResLimit {  // the dynamic-LDS limit set for a kernel on a device: only ever raised
+  int dev = -1;
+  const void *kernel = nullptr;
+  int64_t bytes = 0;
+};
+
 template <class KERNEL>
 int res_grid(KERNEL kernel, int64_t nwaves, int64_t tab_bytes) {
   const char *env = std::getenv("DLM_SHELL_RESIDENT");
@@ -465,18 +480,43 @@ int res_grid(KERNEL kernel, int64_t nwaves, int64_t tab_bytes) {
   if (tab_bytes > kResLdsMax || tab_bytes % 16 != 0) return 0;
   const int cus = device_cus();
   if (cus <= 0 || nwaves < kResMinItems * cus) return 0;
-  if (tab_bytes > 64 * 1024 &&
-      hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)tab_bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    return 0;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  const void *k = reinterpret_cast<const void *>(kernel);
+  static std::mutex mu;
+  static ResFit fits[32];
+  static ResLimit limits[16];
+  static int nfits = 0, nlimits = 0;
+  std::lock_guard<std::mutex> lk(mu);
+  int per_cu = -1;
+  for (int i = 0; i < nfits; ++i)
+    if (fits[i].dev == dev && fits[i].kernel == k && fits[i].bytes == tab_bytes) per_cu = fits[i].per_cu;
+  if (per_cu < 0) {
+    if (nfits == 32) return 0;  // more table sizes than the cache holds: short blocks
+    bool ok = true;
+    if (tab_bytes > 64 * 1024) {
+      int li = -1;
+      for (int i = 0; i < nlimits; ++i)
+        if (limits[i].dev == dev && limits[i].kernel == k) li = i;
+      if (li < 0 && nlimits < 16) {
+        li = nlimits++;
+        limits[li] = ResLimit{dev, k, 64 * 1024};
+      }
+      if (li < 0) return 0;
+      if (limits[li].bytes < tab_bytes) {
+        ok = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tab_bytes) == hipSuccess;
+        if (ok) limits[li].bytes = tab_bytes;
+      }
+    }
+    per_cu = 0;
+    if (ok && (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64 * kResWaves, (size_t)tab_bytes) !=
+                   hipSuccess ||
+               per_cu < 0))
+      per_cu = 0;
+    if (!ok || per_cu == 0) (void)hipGetLastError();
+    fits[nfits++] = ResFit{dev, k, tab_bytes, per_cu};
   }
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64 * kResWaves, (size_t)tab_bytes) != hipSuccess ||
-      per_cu <= 0) {
-    (void)hipGetLastError();
-    return 0;
-  }
+  if (per_cu <= 0) return 0;
   if (nwaves < kResMinItems * cus * per_cu) per_cu = 1;
   return cus * per_cu;
 }

@@ -92,3 +92,31 @@ def test_resident_tables_match_short_blocks_and_oracle(prec, kind):
     errs["loss"] = abs(loss.item() - l_ref) / l_ref
     print(f"[parity] resident tables {kind} {prec}, V={V}: " + fmt(errs), flush=True)
     assert errs["loss"] <= TOL[prec]
+
+
+def test_resident_loss_head_across_table_sizes():
+    """The resident FP32 loss head raises the kernel's dynamic-LDS limit to
+    the largest table it has met and caches its fit per table size: a
+    three-shell plan (110 KB of tables), then a two-shell plan (74 KB), then
+    the three-shell plan again must all run resident and match the oracle
+    (a limit lowered for the two-shell plan would make the third launch
+    fail)."""
+    w = dg.C2
+    three = dg.make_acquisition(w.config, w.shell_b, w.dirs_per_shell, w.perturb_deg, w.n_b0)
+    two = dg.make_acquisition(w.config, w.shell_b[:2], w.dirs_per_shell, w.perturb_deg, w.n_b0)
+    rng = np.random.default_rng(78)
+    for acq, V in ((three, V_BIG), (two, 2 * V_BIG), (three, V_BIG)):
+        oplan = osh.SHPlan(acq.bvecs, acq.bvals, 8, 0.006)
+        plan = dl.SHPlan(acq.bvecs, acq.bvals, 8, 0.006)
+        c = rng.standard_normal((V, len(plan.shells), plan.K)).astype(np.float32).astype(np.float64)
+        tgt = osh.sh2signal(oplan, rng.standard_normal(c.shape)).astype(np.float32).astype(np.float64)
+        loss, dc, xhat = dl.sh2signal_mse_fwd_bwd(plan, cuda(c), cuda(tgt), need_xhat=True, precision="fp32")
+        torch.cuda.synchronize()
+        x_ref = osh.sh2signal(oplan, c)
+        l_ref, dxh_ref = ostack.mse(x_ref, tgt)
+        errs = {}
+        check("xhat", xhat, x_ref, "fp32", errs)
+        check("dc", dc, osh.sh2signal_adjoint(oplan, dxh_ref), "fp32", errs)
+        errs["loss"] = abs(loss.item() - l_ref) / l_ref
+        print(f"[parity] resident loss head, {len(plan.shells)} shells, V={V}: " + fmt(errs), flush=True)
+        assert errs["loss"] <= TOL["fp32"]
