@@ -79,7 +79,7 @@ class SRc:
     """Row-contiguous float32 (k-major): element (r, k) at p[k * ld + r];
     row `ones` reads as 1 (set in registers).  A stage is stored in windows
     of 16 rows of one k; window (k, rg) at index 4 ((4 h + j) NG + rg) + c(k)
-    with k = 16 h + 4 q + j and c(k) = 2 bit3 + (bit2 xor bit4)."""
+    with k = 16 h + 4 q + j and c(k) = (bit2 xor bit3) + 2 (bit3 xor bit4)."""
 
     def __init__(self, vec, ld, rows, ones):
         self.vec, self.ld, self.rows, self.ones = vec, ld, rows, ones
@@ -92,7 +92,8 @@ class SRc:
 
     @staticmethod
     def cls(k):
-        return 2 * ((k >> 3) & 1) + (((k >> 2) ^ (k >> 4)) & 1)
+        b2, b3, b4 = (k >> 2) & 1, (k >> 3) & 1, (k >> 4) & 1
+        return (b2 ^ b3) + 2 * (b3 ^ b4)
 
     def kr(self, s, BR):
         ng = BR // 16
@@ -100,7 +101,10 @@ class SRc:
         idx, c = w >> 2, w & 3
         hj, rg = divmod(idx, ng)
         h, j = hj >> 2, hj & 3
-        k = 16 * h + 8 * (c >> 1) + 4 * ((c & 1) ^ h) + j
+        b3 = (c >> 1) ^ h
+        b2 = (c & 1) ^ b3
+        k = 16 * h + 8 * b3 + 4 * b2 + j
+        assert self.cls(k) == c
         return k, 16 * rg + t
 
     def k_of(self, s, BR):
@@ -128,15 +132,15 @@ class SRc:
         return 64 * ((4 * h + j) * (BR // 16) + rg) + 16 * c + q16
 
     def frag(self, BR, rg, q16, g4):
-        h = g4 >> 1
-        clo, chi = 2 * (g4 & 1) + h, 2 * (g4 & 1) + (1 ^ h)
+        h, b3 = g4 >> 1, g4 & 1
+        clo, chi = b3 + 2 * (b3 ^ h), (1 ^ b3) + 2 * (b3 ^ h)
         r = rg * 16 + q16
         out = [(self.at(BR, h, e, clo, rg, q16), (r, 8 * g4 + e)) for e in range(4)]
         out += [(self.at(BR, h, e, chi, rg, q16), (r, 8 * g4 + 4 + e)) for e in range(4)]
         return out
 
     def frag4(self, BR, rg, q16, g4, h):
-        c = 2 * (g4 >> 1) + ((g4 & 1) ^ h)
+        c = ((g4 & 1) ^ (g4 >> 1)) + 2 * ((g4 >> 1) ^ h)
         r = rg * 16 + q16
         return [(self.at(BR, h, j, c, rg, q16), (r, 16 * h + 4 * g4 + j)) for j in range(4)]
 
@@ -320,18 +324,22 @@ def lane_reads(op, BR, f32):
 # chunks around the k-line and conflicts two ways there; it stays correct.
 @pytest.mark.parametrize("kind,BR", [(k, b) for k, b in LAYOUTS if k.startswith("SR") and (k, b) != ("SRb", 144)])
 def test_element_reads_are_free_of_bank_conflicts(kind, BR):
-    """The row-contiguous operands read their fragments one element per lane
-    (32-bit float32 or 16-bit bfloat16 reads).  Over 64 banks of 4 bytes, the
-    lanes of each read instruction either hit different banks or the same
-    dword (a broadcast), for the FP32 and the BF16 fragment alike."""
+    """The row-contiguous operands read their fragments one dword per lane
+    (float32 values; bfloat16 rows read as the dword holding a row pair).
+    Each read instruction is checked in two bank models: 64 banks of 4 bytes
+    over all 64 lanes, and 32 banks over each half-wave (lanes 0-31, 32-63)
+    -- the one the conflict counters follow for these reads.  In both, the
+    lanes hit different banks or the same dword (a broadcast), for the FP32
+    and the BF16 fragment alike."""
     op = make(kind)
     for f32 in ((False, True) if kind.startswith("SRc") else (False,)):
         for addrs in lane_reads(op, BR, f32):
-            dword = {}
-            for a in addrs:
-                d = a * op.esize // 4
-                bank = d % 64
-                assert dword.setdefault(bank, d) == d, (kind, BR, f32, bank, addrs)
+            for banks, groups in ((64, (range(64),)), (32, (range(32), range(32, 64)))):
+                for lanes in groups:
+                    dword = {}
+                    for lane in lanes:
+                        d = addrs[lane] * op.esize // 4
+                        assert dword.setdefault(d % banks, d) == d, (kind, BR, f32, banks, lane)
 
 
 @pytest.mark.parametrize("kind", ["SKc16", "SKc4", "SKh"])
