@@ -1125,6 +1125,14 @@ constexpr int side_bytes() {
   return b > 0 ? b : 16;
 }
 
+// Two floats rounded to bfloat16 (nearest even) and packed, lo in the low
+// half: one v_cvt_pk_bf16_f32.
+__device__ __forceinline__ uint32_t pack2_bf16(float lo, float hi) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 h2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2{lo, hi}, h2));
+}
+
 // The 16-bit ReLU word of one row's 16-column tile: each of the row's four
 // lanes (q16, g4) holds the nibble of its four columns; two row swaps OR
 // them together in every lane.
@@ -1351,11 +1359,12 @@ __global__ __launch_bounds__(256) void astat_kernel(const float *A, int64_t lda,
           nib[j] = 0;
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
-            const uint16_t lo = to_bf16_bits(v[j][2 * q]), hi = to_bf16_bits(v[j][2 * q + 1]);
-            h2[j][q] = (uint32_t)lo | ((uint32_t)hi << 16);
+            // both values rounded (RNE) by one packed conversion
+            const uint32_t w = pack2_bf16(v[j][2 * q], v[j][2 * q + 1]);
+            h2[j][q] = w;
             if constexpr (kBitsOut)  // the stored (rounded) value is > 0
-              nib[j] |= ((__builtin_bit_cast(float, (uint32_t)lo << 16) > 0.0f ? 1u : 0u) |
-                         (__builtin_bit_cast(float, (uint32_t)hi << 16) > 0.0f ? 2u : 0u))
+              nib[j] |= ((__builtin_bit_cast(float, w << 16) > 0.0f ? 1u : 0u) |
+                         (__builtin_bit_cast(float, w & 0xffff0000u) > 0.0f ? 2u : 0u))
                         << (2 * q);
           }
         }
