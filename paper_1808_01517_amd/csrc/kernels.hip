@@ -230,31 +230,14 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(AL al, BL bl, CS cs, int6
 }
 
 // ------------------------------------------------------------- BF16 core
-// LDS holds both operands row-major with 32 bfloat16 per row (k
-// contiguous) so each lane reads its 8 consecutive k with one 128-bit
-// load: a fragment read takes one 16-byte chunk of 16 consecutive rows.
-// Every operand moves as 16-byte runs of 4 floats (k-contiguous: 4 k of one
-// row; row-contiguous: 4 rows of one k); conversion to bfloat16 (round to
-// nearest even) happens when a run is written to LDS as 8 bytes.  bfloat16
-// tables arrive as 8-byte runs of 4 k.
-//   k-contiguous operands (8 lanes fill a row): rows of 16 dwords, chunk c
-// of row r at c ^ f(r), f(r) = bit1 ^ 2 bit2 ^ bit3 of r.  The stores of 4
-// consecutive rows cover the 64 banks once; a fragment read covers them
-// once per 16 lanes, and 32 banks once per 8 lanes.  (The padded layout
-// below put rows 20 dwords apart, so the stores of rows r and r + 3
-// shared banks.)
-//   row-contiguous operands (a lane fills 4 rows at one k): rows of 20
-// dwords, chunk c of row r at c ^ ((r >> 4) & 3).
-template <bool KC>
-__device__ __forceinline__ int bf16_slot(int row, int k) {
-  if constexpr (KC) {
-    const int f = ((row >> 1) & 1) ^ (((row >> 2) & 1) << 1) ^ ((row >> 3) & 1);
-    return row * 32 + 8 * ((k >> 3) ^ f) + (k & 7);
-  } else {
-    return row * 40 + 8 * ((k >> 3) ^ ((row >> 4) & 3)) + (k & 7);
-  }
-}
-
+// LDS holds both operands row-major with BK bfloat16 per row (k
+// contiguous, row stride BK+8) so each lane reads its 8 consecutive k with
+// one 128-bit load.  The 16-byte chunk c of row r is stored at chunk
+// c ^ ((r >> 4) & 3), which keeps both the staging stores and the MFMA
+// reads free of bank conflicts.  Every operand moves as 16-byte runs of 4
+// floats (k-contiguous: 4 k of one row; row-contiguous: 4 rows of one k);
+// conversion to bfloat16 (round to nearest even) happens when a run is
+// written to LDS.  bfloat16 tables arrive as 8-byte runs of 4 k.
 __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
   return (uint32_t)to_bf16_bits(lo) | ((uint32_t)to_bf16_bits(hi) << 16);
 }
@@ -262,9 +245,8 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
 template <int OP, class CF, class AL, class BL, class CS>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int64_t M, int N, int K, int ksplit,
                                                         int nbM, int nbN, int nz) {
-  constexpr int BM = CF::BM, BN = CF::BN, BK = 32;
+  constexpr int BM = CF::BM, BN = CF::BN, BK = 32, LD = BK + 8;
   constexpr bool AK = AL::kContig, BKC = BL::kContig;
-  constexpr int LDA = AK ? BK : BK + 8, LDB = BKC ? BK : BK + 8;  // the layouts of bf16_slot
   constexpr bool BT = std::is_same<typename BL::type, uint16_t>::value;
   static_assert(!BT || BKC, "bfloat16 tables are k-contiguous");
   using RA = Runs<AL, BM, BK>;
@@ -274,8 +256,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
   constexpr int NB = BKC ? RB::NRUN : RB::NRUN / 4;
   constexpr int PA = (NA + 255) / 256, PB = (NB + 255) / 256;
   constexpr int QA = AK ? 1 : 4, QB = BKC ? 1 : 4;
-  __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LDA];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LDB];
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % CF::WM, wn = wave / CF::WM;
   const int q16 = lane & 15, g4 = lane >> 4;
@@ -296,8 +278,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
   auto coordB = [&](int e, int &col, int &kk) {
     if constexpr (BKC) { kk = 4 * (e % (BK / 4)); col = e / (BK / 4); } else { col = 4 * (e % (BN / 4)); kk = 4 * (e / (BN / 4)); }
   };
-  auto swA = [&](int row, int k) { return bf16_slot<AK>(row, k); };
-  auto swB = [&](int row, int k) { return bf16_slot<BKC>(row, k); };
+  auto sw = [&](int row, int k) { return row * LD + 8 * ((k >> 3) ^ ((row >> 4) & 3)) + (k & 7); };
   auto load = [&](int k0) {
 #pragma unroll
     for (int p = 0; p < PA; ++p) {
@@ -339,12 +320,12 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
       coordA(e, row, kk);
       if constexpr (AK) {
         const floatx4 v = RA::finish(ra[p][0], ma[p][0]);
-        *reinterpret_cast<uint2 *>(&As[buf][swA(row, kk)]) = make_uint2(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]));
+        *reinterpret_cast<uint2 *>(&As[buf][sw(row, kk)]) = make_uint2(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]));
       } else {
         floatx4 v[4];
         for (int q = 0; q < 4; ++q) v[q] = RA::finish(ra[p][q], ma[p][q]);
         for (int i = 0; i < 4; ++i)
-          *reinterpret_cast<uint2 *>(&As[buf][swA(row + i, kk)]) =
+          *reinterpret_cast<uint2 *>(&As[buf][sw(row + i, kk)]) =
               make_uint2(pack_bf16(v[0][i], v[1][i]), pack_bf16(v[2][i], v[3][i]));
       }
     }
@@ -355,15 +336,15 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
       int col, kk;
       coordB(e, col, kk);
       if constexpr (BT) {
-        *reinterpret_cast<uint2 *>(&Bs[buf][swB(col, kk)]) = rt[p];
+        *reinterpret_cast<uint2 *>(&Bs[buf][sw(col, kk)]) = rt[p];
       } else if constexpr (BKC) {
         const floatx4 v = RB::finish(rb[p][0], mb[p][0]);
-        *reinterpret_cast<uint2 *>(&Bs[buf][swB(col, kk)]) = make_uint2(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]));
+        *reinterpret_cast<uint2 *>(&Bs[buf][sw(col, kk)]) = make_uint2(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]));
       } else {
         floatx4 v[4];
         for (int q = 0; q < 4; ++q) v[q] = RB::finish(rb[p][q], mb[p][q]);
         for (int i = 0; i < 4; ++i)
-          *reinterpret_cast<uint2 *>(&Bs[buf][swB(col + i, kk)]) =
+          *reinterpret_cast<uint2 *>(&Bs[buf][sw(col + i, kk)]) =
               make_uint2(pack_bf16(v[0][i], v[1][i]), pack_bf16(v[2][i], v[3][i]));
       }
     }
@@ -386,10 +367,10 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(AL al, BL bl, CS cs, int
     bf16x8 a[CF::TM], b[CF::TN];
 #pragma unroll
     for (int i = 0; i < CF::TM; ++i)
-      a[i] = *reinterpret_cast<const bf16x8 *>(&As[cur][swA((wm * CF::TM + i) * 16 + q16, 8 * g4)]);
+      a[i] = *reinterpret_cast<const bf16x8 *>(&As[cur][sw((wm * CF::TM + i) * 16 + q16, 8 * g4)]);
 #pragma unroll
     for (int j = 0; j < CF::TN; ++j)
-      b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[cur][swB((wn * CF::TN + j) * 16 + q16, 8 * g4)]);
+      b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[cur][sw((wn * CF::TN + j) * 16 + q16, 8 * g4)]);
 #pragma unroll
     for (int i = 0; i < CF::TM; ++i)
 #pragma unroll

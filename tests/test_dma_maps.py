@@ -572,46 +572,3 @@ def test_short_reduction_waits_never_cover_a_dma_in_flight(f32, D, N):
             if t + D < NT:
                 log += [("dma", t + D)] * nq
             log += [("st", t)] * stores
-
-
-# --------------------------------------------------------------------------
-# Register-staged BF16 core: LDS position of entry k of a tile row
-# (bf16_slot in csrc/kernels.hip), restated.
-
-def bf16_slot(kc, row, k):
-    if kc:
-        f = ((row >> 1) & 1) ^ (((row >> 2) & 1) << 1) ^ ((row >> 3) & 1)
-        return row * 32 + 8 * ((k >> 3) ^ f) + (k & 7)
-    return row * 40 + 8 * ((k >> 3) ^ ((row >> 4) & 3)) + (k & 7)
-
-
-@pytest.mark.parametrize("rows", [16, 48, 64, 96, 128, 144])
-def test_bf16_core_k_contiguous_layout(rows):
-    """k-contiguous operands of the BF16 core: each (row, k) of a tile of 32 k
-    has its own bfloat16 slot inside rows x 32; the 8-byte staging stores of a
-    wave (lane l: row 8w + l / 8, k 4 (l % 8)) put every 4 consecutive rows
-    on the 64 banks once and every 2 rows on 32 banks once; a fragment read
-    (16 consecutive rows from a multiple of 16, 16-byte chunk g4) covers 64
-    banks once per 16 lanes and 32 banks once per 8 lanes."""
-    slots = {bf16_slot(True, r, k) for r in range(rows) for k in range(32)}
-    assert slots == set(range(rows * 32))
-    dword = lambda s: s // 2
-    for r0 in range(0, rows - 3, 4):  # stores: 8 lanes a row, 2 dwords each
-        banks = [(dword(bf16_slot(True, r, 4 * c)) + i) % 64 for r in range(r0, r0 + 4) for c in range(8) for i in range(2)]
-        assert sorted(banks) == list(range(64))
-        for h in (0, 2):
-            banks = [(dword(bf16_slot(True, r, 4 * c)) + i) % 32 for r in range(r0 + h, r0 + h + 2) for c in range(8) for i in range(2)]
-            assert sorted(banks) == list(range(32))
-    for r0 in range(0, rows - 15, 16):  # fragment reads: 16 bytes a lane
-        for g4 in range(4):
-            d = [dword(bf16_slot(True, r0 + q, 8 * g4)) for q in range(16)]
-            assert all(bf16_slot(True, r0 + q, 8 * g4 + e) == 2 * d[q] + e for q in range(16) for e in range(8))
-            assert sorted((x + i) % 64 for x in d for i in range(4)) == list(range(64))
-            for h in (0, 8):
-                assert sorted((x + i) % 32 for x in d[h:h + 8] for i in range(4)) == list(range(32))
-
-
-def test_bf16_core_row_contiguous_layout_is_a_bijection():
-    for rows in (48, 64, 128, 144):
-        slots = {bf16_slot(False, r, k) for r in range(rows) for k in range(32)}
-        assert len(slots) == rows * 32 and max(slots) < rows * 40
