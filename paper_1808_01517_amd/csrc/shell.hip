@@ -8,10 +8,12 @@
 // directions per shell).  Such a contraction is a stream: 15 flop per byte
 // against a bf16 ridge near 300, so the design keeps the loads flowing and
 // nothing else in the way:
-// * one wave computes 16 voxels x one shell; its A fragments are loaded
-//   straight from HBM into registers (16-byte loads along the voxel's row,
-//   all issued before the first MFMA), so there is no LDS staging and no
-//   barrier, and many resident waves hide the latency;
+// * one wave computes 16 voxels x one shell (BF16 contractions over the
+//   coefficients: two such blocks of the same shell, sharing each table
+//   fragment); its A fragments are loaded straight from HBM into registers
+//   (16-byte loads along the voxel's row, all issued before the first
+//   MFMA), so there is no LDS staging and no barrier, and many resident
+//   waves hide the latency;
 // * the table Bt_g arrives pre-arranged on the host in MFMA fragment order,
 //   one 16-byte load per lane per fragment (it stays in L1/L2).  The FP32
 //   loss head on large batches runs as persistent 1024-thread blocks that
@@ -55,33 +57,59 @@ __device__ __forceinline__ floatx4 load_run(const float *a, int k, int kend, boo
   return v;
 }
 
-template <int OP, bool F32>
+template <int OP, bool F32, int MAXRED, int IT>
 __global__ __launch_bounds__(256) void shell_gemm_kernel(const float *A, int64_t lda, int64_t a_gs, float *C,
                                                          int64_t ldc, int64_t c_gs, const void *frag,
                                                          int64_t frag_gs, int ncol, int nred, int groups, int64_t V,
                                                          int64_t nwaves) {
+  // IT row blocks of 16 voxels of one shell per wave: every block's loads
+  // are issued before the first MFMA and each table fragment serves all of
+  // them.  MAXRED bounds the reduction (registers for A are sized by it).
   const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (w >= nwaves) return;  // whole waves only; no barriers in this kernel
   const int lane = threadIdx.x & 63, q16 = lane & 15, g4 = lane >> 4;
   const int64_t rb = w / groups;
   const int g = (int)(w - rb * groups);
-  const int64_t r = rb * 16 + q16;
-  const bool row = r < V;
-  const float *a = A + r * lda + (int64_t)g * a_gs;
-  float *c = C + r * ldc + (int64_t)g * c_gs;
+  const float *a[IT];
+  float *c[IT];
+  bool row[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int64_t r = (rb * IT + it) * 16 + q16;
+    row[it] = r < V;
+    a[it] = A + r * lda + (int64_t)g * a_gs;
+    c[it] = C + r * ldc + (int64_t)g * c_gs;
+  }
   const int NT = (ncol + 15) / 16;
+  auto store = [&](int it, int j0, int nt, const floatx4 (&acc)[kColChunk]) {
+    if (!row[it]) return;
+#pragma unroll
+    for (int j = 0; j < kColChunk; ++j) {
+      if (j >= nt) break;
+      const int n = 16 * (j0 + j) + 4 * g4;
+      if (n + 3 < ncol) __builtin_memcpy(c[it] + n, &acc[j], 16);
+      else
+        for (int e = 0; e < 4; ++e)
+          if (n + e < ncol) c[it][n + e] = acc[j][e];
+    }
+  };
   if constexpr (F32) {
-    constexpr int HM = kMaxRed / 16;
+    constexpr int HM = MAXRED / 16;
     const int H = (nred + 15) / 16;
     const floatx4 *fr = reinterpret_cast<const floatx4 *>(frag) + (int64_t)g * frag_gs / 16;
-    floatx4 av[HM];
+    floatx4 av[IT][HM];
 #pragma unroll
-    for (int h = 0; h < HM; ++h) av[h] = h < H ? load_run(a, 16 * h + 4 * g4, nred, row) : floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int it = 0; it < IT; ++it)
+#pragma unroll
+      for (int h = 0; h < HM; ++h)
+        av[it][h] = h < H ? load_run(a[it], 16 * h + 4 * g4, nred, row[it]) : floatx4{0.f, 0.f, 0.f, 0.f};
     for (int j0 = 0; j0 < NT; j0 += kColChunk) {
       const int nt = min(kColChunk, NT - j0);
-      floatx4 acc[kColChunk];
+      floatx4 acc[IT][kColChunk];
 #pragma unroll
-      for (int j = 0; j < kColChunk; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int it = 0; it < IT; ++it)
+#pragma unroll
+        for (int j = 0; j < kColChunk; ++j) acc[it][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int h = 0; h < HM; ++h) {
         if (h >= H) break;
@@ -90,44 +118,44 @@ __global__ __launch_bounds__(256) void shell_gemm_kernel(const float *A, int64_t
           if (j >= nt) break;
           const floatx4 b = fr[((int64_t)(j0 + j) * H + h) * 64 + lane];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[e], av[h][e], acc[j], 0, 0, 0);
-        }
-      }
-      if (row) {
+          for (int it = 0; it < IT; ++it)
 #pragma unroll
-        for (int j = 0; j < kColChunk; ++j) {
-          if (j >= nt) break;
-          const int n = 16 * (j0 + j) + 4 * g4;
-          if (n + 3 < ncol) __builtin_memcpy(c + n, &acc[j], 16);
-          else
             for (int e = 0; e < 4; ++e)
-              if (n + e < ncol) c[n + e] = acc[j][e];
+              acc[it][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[e], av[it][h][e], acc[it][j], 0, 0, 0);
         }
       }
+#pragma unroll
+      for (int it = 0; it < IT; ++it) store(it, j0, nt, acc[it]);
     }
   } else {
-    constexpr int SM = kMaxRed / 32;
+    constexpr int SM = MAXRED / 32;
     const int S = (nred + 31) / 32;
     const bf16x8 *fr = reinterpret_cast<const bf16x8 *>(frag) + (int64_t)g * frag_gs / 16;
-    floatx4 lo[SM], hi[SM];
+    floatx4 lo[IT][SM], hi[IT][SM];
 #pragma unroll
-    for (int s = 0; s < SM; ++s) {
-      lo[s] = s < S ? load_run(a, 32 * s + 8 * g4, nred, row) : floatx4{0.f, 0.f, 0.f, 0.f};
-      hi[s] = s < S ? load_run(a, 32 * s + 8 * g4 + 4, nred, row) : floatx4{0.f, 0.f, 0.f, 0.f};
-    }
-    bf16x8 av[SM];
+    for (int it = 0; it < IT; ++it)
 #pragma unroll
-    for (int s = 0; s < SM; ++s)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        av[s][e] = (__bf16)lo[s][e];
-        av[s][4 + e] = (__bf16)hi[s][e];
+      for (int s = 0; s < SM; ++s) {
+        lo[it][s] = s < S ? load_run(a[it], 32 * s + 8 * g4, nred, row[it]) : floatx4{0.f, 0.f, 0.f, 0.f};
+        hi[it][s] = s < S ? load_run(a[it], 32 * s + 8 * g4 + 4, nred, row[it]) : floatx4{0.f, 0.f, 0.f, 0.f};
       }
+    bf16x8 av[IT][SM];
+#pragma unroll
+    for (int it = 0; it < IT; ++it)
+#pragma unroll
+      for (int s = 0; s < SM; ++s)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          av[it][s][e] = (__bf16)lo[it][s][e];
+          av[it][s][4 + e] = (__bf16)hi[it][s][e];
+        }
     for (int j0 = 0; j0 < NT; j0 += kColChunk) {
       const int nt = min(kColChunk, NT - j0);
-      floatx4 acc[kColChunk];
+      floatx4 acc[IT][kColChunk];
 #pragma unroll
-      for (int j = 0; j < kColChunk; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int it = 0; it < IT; ++it)
+#pragma unroll
+        for (int j = 0; j < kColChunk; ++j) acc[it][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < SM; ++s) {
         if (s >= S) break;
@@ -135,36 +163,43 @@ __global__ __launch_bounds__(256) void shell_gemm_kernel(const float *A, int64_t
         for (int j = 0; j < kColChunk; ++j) {
           if (j >= nt) break;
           const bf16x8 b = fr[((int64_t)(j0 + j) * S + s) * 64 + lane];
-          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, av[s], acc[j], 0, 0, 0);
-        }
-      }
-      if (row) {
 #pragma unroll
-        for (int j = 0; j < kColChunk; ++j) {
-          if (j >= nt) break;
-          const int n = 16 * (j0 + j) + 4 * g4;
-          if (n + 3 < ncol) __builtin_memcpy(c + n, &acc[j], 16);
-          else
-            for (int e = 0; e < 4; ++e)
-              if (n + e < ncol) c[n + e] = acc[j][e];
+          for (int it = 0; it < IT; ++it)
+            acc[it][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, av[it][s], acc[it][j], 0, 0, 0);
         }
       }
+#pragma unroll
+      for (int it = 0; it < IT; ++it) store(it, j0, nt, acc[it]);
     }
   }
 }
 
-template <int OP>
-int launch_op(const ShellGemm &t, dlm_precision prec, hipStream_t st) {
-  const int64_t nwaves = (t.V + 15) / 16 * t.groups;
+// Reductions of at most 64 entries (every contraction over a shell's
+// coefficients up to order 12) size A's registers for 64.  BF16 takes two
+// row blocks per wave, FP32 one (measured on the three-shell Signal2SH
+// adjoint at 1M voxels: BF16 0.448 -> 0.419 ms with two, 0.481 with one;
+// FP32 0.559 -> 0.554 ms with one, 0.559 with two).
+template <int OP, bool F32, int MAXRED, int IT>
+int launch_op_t(const ShellGemm &t, const void *frag, int64_t frag_gs, hipStream_t st) {
+  const int64_t nwaves = ((t.V + 15) / 16 + IT - 1) / IT * t.groups;
   const int64_t blocks = (nwaves + 3) / 4;
   if (blocks > 0x7fffffff) return -4;
-  if (prec == DLM_BF16)
-    hipLaunchKernelGGL((shell_gemm_kernel<OP, false>), dim3((unsigned)blocks), dim3(256), 0, st, t.A, t.lda, t.a_gs,
-                       t.C, t.ldc, t.c_gs, (const void *)t.frag_h, t.frag_gs_h, t.ncol, t.nred, t.groups, t.V, nwaves);
-  else
-    hipLaunchKernelGGL((shell_gemm_kernel<OP, true>), dim3((unsigned)blocks), dim3(256), 0, st, t.A, t.lda, t.a_gs,
-                       t.C, t.ldc, t.c_gs, (const void *)t.frag_f, t.frag_gs_f, t.ncol, t.nred, t.groups, t.V, nwaves);
+  hipLaunchKernelGGL((shell_gemm_kernel<OP, F32, MAXRED, IT>), dim3((unsigned)blocks), dim3(256), 0, st, t.A, t.lda,
+                     t.a_gs, t.C, t.ldc, t.c_gs, frag, frag_gs, t.ncol, t.nred, t.groups, t.V, nwaves);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int OP>
+int launch_op(const ShellGemm &t, dlm_precision prec, hipStream_t st) {
+  const bool bf = prec == DLM_BF16;
+  const void *frag = bf ? (const void *)t.frag_h : (const void *)t.frag_f;
+  const int64_t gs = bf ? t.frag_gs_h : t.frag_gs_f;
+  if (t.nred <= 64) {
+    if (bf) return launch_op_t<OP, false, 64, 2>(t, frag, gs, st);
+    return launch_op_t<OP, true, 64, 1>(t, frag, gs, st);
+  }
+  if (bf) return launch_op_t<OP, false, kMaxRed, 1>(t, frag, gs, st);
+  return launch_op_t<OP, true, kMaxRed, 1>(t, frag, gs, st);
 }
 
 // SH2Signal -> q-space MSE -> SH2Signal adjoint for 16 voxels x one shell
