@@ -540,9 +540,10 @@ dlm_status sh_apply(const dlm_sh_plan *p, const float *in, float *out, int64_t V
     int rc = 0;
     // one wave per 16 voxels x shell (tables in fragment order) for the
     // contractions over the coefficients (K <= 64: Signal2SH adjoint,
-    // SH2Signal), and for FP32 Signal2SH on large batches in its
-    // table-resident form; other reductions over a shell's directions keep
-    // the tiled core, which measured faster for them
+    // SH2Signal), for FP32 Signal2SH on large batches in its table-resident
+    // form, and for BF16 reductions over up to 96 directions (Signal2SH,
+    // SH2Signal adjoint) on large batches; the rest keep the tiled core,
+    // which measured faster for them
     bool shell = false;
     if (shell_gemm_ok(t.N, t.K)) {
       const int ti = int(op);
@@ -562,7 +563,7 @@ dlm_status sh_apply(const dlm_sh_plan *p, const float *in, float *out, int64_t V
       g.groups = t.groups;
       g.V = V;
       g.op = t.op;
-      shell = t.K <= 64 || shell_s2sh_resident(g, prec);
+      shell = t.K <= 64 || shell_s2sh_resident(g, prec) || shell_long_bf16(g, prec);
       if (shell) rc = launch_shell_gemm(g, prec, stream);
     }
     if (!shell) rc = launch_table_gemm(t, prec, stream);

@@ -126,6 +126,9 @@ int launch_shell_gemm(const ShellGemm &g, dlm_precision prec, void *stream);
 // Whether launch_shell_gemm runs g (a Signal2SH contraction) in the
 // table-resident FP32 form: FP32, nred <= 128 and a batch large enough.
 bool shell_s2sh_resident(const ShellGemm &g, dlm_precision prec);
+// BF16 reduction over 65..96 directions on a batch large enough for the
+// per-shell kernel's two-block waves (otherwise the tiled core runs it)
+bool shell_long_bf16(const ShellGemm &t, dlm_precision prec);
 size_t shell_frag_floats(int ncol, int nred);
 size_t shell_frag_halves(int ncol, int nred);
 void shell_frag_tables(const double *t, int ncol, int nred, float *f, uint16_t *h);
