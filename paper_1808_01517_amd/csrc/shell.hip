@@ -179,6 +179,15 @@ __global__ __launch_bounds__(256) void shell_gemm_kernel(const float *A, int64_t
 // row blocks per wave, FP32 one (measured on the three-shell Signal2SH
 // adjoint at 1M voxels: BF16 0.448 -> 0.419 ms with two, 0.481 with one;
 // FP32 0.559 -> 0.554 ms with one, 0.559 with two).
+// DLM_SHELL_PAIRS=0 in the environment gives these BF16 contractions one
+// 16-voxel block per wave instead of two (the same results bit for bit;
+// read at every call, for tests).  The loss head keeps one block per wave:
+// with two it measured 0.646 -> 0.869 ms.
+inline bool bf16_pairs() {
+  const char *e = std::getenv("DLM_SHELL_PAIRS");
+  return !(e && e[0] == '0');
+}
+
 template <int OP, bool F32, int MAXRED, int IT>
 int launch_op_t(const ShellGemm &t, const void *frag, int64_t frag_gs, hipStream_t st) {
   const int64_t nwaves = ((t.V + 15) / 16 + IT - 1) / IT * t.groups;
@@ -195,10 +204,13 @@ int launch_op(const ShellGemm &t, dlm_precision prec, hipStream_t st) {
   const void *frag = bf ? (const void *)t.frag_h : (const void *)t.frag_f;
   const int64_t gs = bf ? t.frag_gs_h : t.frag_gs_f;
   if (t.nred <= 64) {
-    if (bf) return launch_op_t<OP, false, 64, 2>(t, frag, gs, st);
+    if (bf) return bf16_pairs() ? launch_op_t<OP, false, 64, 2>(t, frag, gs, st)
+                                : launch_op_t<OP, false, 64, 1>(t, frag, gs, st);
     return launch_op_t<OP, true, 64, 1>(t, frag, gs, st);
   }
-  if (bf && t.nred <= 96) return launch_op_t<OP, false, 96, 2>(t, frag, gs, st);  // see shell_long_bf16
+  if (bf && t.nred <= 96)  // see shell_long_bf16
+    return bf16_pairs() ? launch_op_t<OP, false, 96, 2>(t, frag, gs, st)
+                        : launch_op_t<OP, false, 96, 1>(t, frag, gs, st);
   if (bf) return launch_op_t<OP, false, kMaxRed, 1>(t, frag, gs, st);
   return launch_op_t<OP, true, kMaxRed, 1>(t, frag, gs, st);
 }
