@@ -1188,6 +1188,7 @@ __global__ __launch_bounds__(256) void astat_kernel(const float *A, int64_t lda,
   constexpr int SW = TM * (kHalf ? (TN + 1) / 2 : TN);
   static_assert(D >= 1 && D <= 3 && D * SW + (D - 1) * IW < 64, "vmcnt range");
   __shared__ __attribute__((aligned(16))) char lds[NS * TILE + side_bytes<CS>()];
+  static_assert((NS * TILE + bias_bytes<CS>()) % 16 == 0, "16-byte aligned bit words in LDS");
   float *sbias = reinterpret_cast<float *>(lds + NS * TILE);
   uint16_t *sbits = reinterpret_cast<uint16_t *>(lds + NS * TILE + bias_bytes<CS>());
 
@@ -1237,11 +1238,20 @@ __global__ __launch_bounds__(256) void astat_kernel(const float *A, int64_t lda,
   if constexpr (CS::kBias)
     for (int c = tid; c < N; c += 256) sbias[c] = cs.bias_n[c];
   if constexpr (kMaskIn) {
-    for (int c = tid; c < BM * wpr; c += 256) {
-      const int rr = c / wpr;
-      int64_t r = m0 + rr;
-      if (r >= M) r = M - 1;
-      sbits[c] = cs.mbits[r * wpr + (c - rr * wpr)];
+    // the block's bit words are one run of memory: 16-byte copies when it
+    // is whole and aligned (LDS side: the tiles and the bias are multiples
+    // of 16 bytes), else word by word with rows clamped
+    const uint16_t *src = cs.mbits + m0 * wpr;
+    if (full && (BM * wpr) % 8 == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+      for (int c = tid; c < BM * wpr / 8; c += 256)
+        __builtin_memcpy(reinterpret_cast<uint4 *>(sbits) + c, reinterpret_cast<const uint4 *>(src) + c, 16);
+    } else {
+      for (int c = tid; c < BM * wpr; c += 256) {
+        const int rr = c / wpr;
+        int64_t r = m0 + rr;
+        if (r >= M) r = M - 1;
+        sbits[c] = cs.mbits[r * wpr + (c - rr * wpr)];
+      }
     }
   }
   wait_barrier<0>();
