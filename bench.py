@@ -516,7 +516,7 @@ def main():
         (bench_c4 if args.workload == "c4" else bench_sweep)(args)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the layers are per-voxel and this build "
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the layers are per-voxel and the benchmark "
               "measures a single GPU's share; see the sharding notes in the design document.", file=sys.stderr)
         sys.exit(2)
     import torch
